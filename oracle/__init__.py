@@ -1,0 +1,31 @@
+"""CPU FP64 oracle for piecewise-constant GRAPE (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product path (the HIP library and its Python
+binding) never imports, calls or links anything here.
+"""
+from .grape import (
+    slice_hamiltonians,
+    expm_herm,
+    slice_propagators,
+    forward_products,
+    backward_products,
+    fidelity,
+    frechet_dk,
+    gradient,
+    grape_ref,
+    fidelity_ref,
+)
+
+__all__ = [
+    "slice_hamiltonians",
+    "expm_herm",
+    "slice_propagators",
+    "forward_products",
+    "backward_products",
+    "fidelity",
+    "frechet_dk",
+    "gradient",
+    "grape_ref",
+    "fidelity_ref",
+]

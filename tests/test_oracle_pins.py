@@ -1,0 +1,262 @@
+"""Pins that fix the CPU oracle to facts outside itself.
+
+Each test checks the oracle against a closed form, an invariant, a library
+routine that uses a different algorithm (scipy's Pade expm / expm_frechet,
+Van Loan's block exponent), or brute-force finite differences.  Together they
+catch a dropped drift term, a wrong sign of i, a reversed product order, a
+transposed or conjugated operand, a wrong fidelity normalisation and a wrong
+slice or control index in the gradient.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from workloads import heisenberg_drift, make_config, pauli, site_op, xy_controls, Problem
+
+SX, SY, SZ = pauli("x"), pauli("y"), pauli("z")
+
+
+def _single_qubit(omega, u, N, dt, V=None):
+    return Problem(0.5 * omega * SZ, SX[None], np.full((1, N), float(u)), dt,
+                   SX if V is None else V)
+
+
+@pytest.mark.parametrize("omega,u", [(1.0, 0.7), (1.0, -0.3), (2.5, 1.9)])
+def test_closed_form_single_qubit_constant_field(omega, u):
+    """H = (w/2) Z + u X for all slices: X_N = cos(bT) I - i sin(bT) (u X + (w/2) Z)/b
+    with b = sqrt(u^2 + w^2/4), T = N dt; for V = X, F = u^2 sin^2(bT) / b^2."""
+    N, dt = 100, 0.01
+    p = _single_qubit(omega, u, N, dt)
+    r = oracle.grape_ref(p)
+    T = N * dt
+    b = np.sqrt(u * u + omega * omega / 4)
+    XN = np.cos(b * T) * np.eye(2) - 1j * np.sin(b * T) * (u * SX + 0.5 * omega * SZ) / b
+    assert np.max(np.abs(r["XN"] - XN)) < 1e-13
+    assert abs(r["F"] - u * u * np.sin(b * T) ** 2 / b ** 2) < 1e-13
+
+
+@pytest.mark.parametrize("cfg,d", [(2, 16), (3, 64), (4, 128)])
+def test_constant_hamiltonian_collapses_to_one_exponential(cfg, d):
+    """u[j, k] = u_j for all k: X_N = expm(-i N dt H), terms commuting or not."""
+    p = make_config(cfg, N=7)
+    uc = np.repeat(p.u[:, :1], 7, axis=1)
+    p = p.with_u(uc)
+    H = p.H0 + np.einsum("j,jab->ab", uc[:, 0], p.Hc)
+    ref = sla.expm(-1j * p.N * p.dt * H)
+    r = oracle.fidelity_ref(p)
+    assert p.d == d
+    assert np.max(np.abs(r["XN"] - ref)) < 1e-12
+
+
+def test_product_order_matches_scipy_per_slice():
+    """Non-commuting slices: X_N = expm(-i dt H_2) expm(-i dt H_1) expm(-i dt H_0)."""
+    p = make_config(2, N=3)
+    Hs = [p.H0 + np.einsum("j,jab->ab", p.u[:, k], p.Hc) for k in range(3)]
+    ref = np.eye(16)
+    for k in range(3):
+        ref = sla.expm(-1j * p.dt * 40 * Hs[k]) @ ref   # larger steps: order matters
+    q = Problem(p.H0, p.Hc, p.u, p.dt * 40, p.V)
+    r = oracle.fidelity_ref(q)
+    assert np.max(np.abs(r["XN"] - ref)) < 1e-12
+    wrong = np.eye(16)
+    for k in range(3):
+        wrong = wrong @ sla.expm(-1j * p.dt * 40 * Hs[k])
+    assert np.max(np.abs(r["XN"] - wrong)) > 1e-3
+
+
+def test_commuting_diagonal_case_is_elementwise():
+    """Diagonal H0 = sum h_i Z_i + sum J_i Z_i Z_{i+1} with Z_i controls:
+    X_N = diag(exp(-i dt sum_k diag(H_k)))."""
+    nq, N, dt = 4, 37, 0.01
+    rng = np.random.default_rng(11)
+    J = rng.uniform(0.5, 1.5, nq - 1)
+    h = rng.normal(0, 0.2, nq)
+    H0 = sum(h[i] * site_op(i, "z", nq) for i in range(nq))
+    H0 = H0 + sum(J[i] * site_op(i, "z", nq) @ site_op(i + 1, "z", nq) for i in range(nq - 1))
+    Hc = np.stack([site_op(i, "z", nq) for i in range(nq)])
+    u = rng.normal(0, 0.5, (nq, N))
+    p = Problem(H0, Hc, u, dt, np.eye(16))
+    r = oracle.fidelity_ref(p)
+    phase = np.diag(H0).real * N + np.einsum("jk,ja->a", u, np.einsum("jaa->ja", Hc).real)
+    ref = np.diag(np.exp(-1j * dt * phase))
+    assert np.max(np.abs(r["XN"] - ref)) < 1e-13
+
+
+def test_unitarity_of_slices_and_products():
+    p = make_config(3, N=60)
+    Us, _, _ = oracle.slice_propagators(p.H0, p.Hc, p.u, p.dt)
+    Xs = oracle.forward_products(Us)
+    eye = np.eye(p.d)
+    for U in Us:
+        assert np.linalg.norm(U.conj().T @ U - eye) < 1e-13
+    assert np.linalg.norm(Xs[-1].conj().T @ Xs[-1] - eye) < 1e-13 * np.sqrt(p.N) * 10
+
+
+def test_trace_invariance_every_slice():
+    """Tr(W_k^dag U_k) = g for every k, W_k = B_{k+1} X_k^dag."""
+    p = make_config(2, N=40)
+    Us, _, _ = oracle.slice_propagators(p.H0, p.Hc, p.u, p.dt)
+    Xs = oracle.forward_products(Us)
+    Bs = oracle.backward_products(Us, p.V)
+    g, _ = oracle.fidelity(p.V, Xs[-1])
+    for k in range(p.N):
+        W = Bs[k + 1] @ Xs[k].conj().T
+        assert abs(np.trace(W.conj().T @ Us[k]) - g) < 1e-12
+
+
+def test_fidelity_invariants():
+    p = make_config(2, N=50)
+    r = oracle.fidelity_ref(p)
+    assert 0.0 <= r["F"] <= 1.0
+    r2 = oracle.fidelity_ref(p.with_target(np.exp(0.77j) * p.V))
+    assert abs(r2["F"] - r["F"]) < 1e-15
+    r3 = oracle.fidelity_ref(p.with_target(r["XN"]))
+    assert abs(r3["F"] - 1.0) < 1e-13
+    # normalisation: F = 1/d^2 |Tr|^2, so V = identity on a trivial evolution gives 1
+    q = Problem(0 * p.H0, p.Hc, 0 * p.u, p.dt, np.eye(p.d))
+    assert abs(oracle.fidelity_ref(q)["F"] - 1.0) < 1e-15
+
+
+def test_commuting_gradient_closed_form():
+    """H0 = 0, one sigma_x control, V = X: Theta = dt sum_k u_k, F = sin^2(Theta),
+    dF/du_k = dt sin(2 Theta) for every k."""
+    p1 = make_config(1)
+    p = Problem(0 * p1.H0, p1.Hc, p1.u, p1.dt, SX)
+    r = oracle.grape_ref(p)
+    th = p.dt * p.u.sum()
+    assert abs(r["F"] - np.sin(th) ** 2) < 1e-14
+    assert np.max(np.abs(r["grad"] - p.dt * np.sin(2 * th))) < 1e-15
+
+
+@pytest.mark.parametrize("omega,u", [(1.0, 0.7), (1.0, -1.3)])
+def test_gradient_sum_rule_constant_field(omega, u):
+    """For constant u: sum_k dF/du_k = dF/du of the closed form
+    F(u) = u^2 s^2 / b^2, s = sin(bT), c = cos(bT), b = sqrt(u^2 + w^2/4)."""
+    N, dt = 100, 0.01
+    r = oracle.grape_ref(_single_qubit(omega, u, N, dt))
+    T = N * dt
+    b = np.sqrt(u * u + omega * omega / 4)
+    s, c = np.sin(b * T), np.cos(b * T)
+    dF = 2 * u * s * s / b ** 2 + 2 * u ** 3 * s * c * T / b ** 3 - 2 * u ** 3 * s * s / b ** 4
+    assert abs(r["grad"].sum() - dF) < 1e-13
+
+
+def test_commuting_gradient_independent_of_slice():
+    nq, N, dt = 4, 25, 0.01
+    rng = np.random.default_rng(5)
+    H0 = sum(rng.normal() * site_op(i, "z", nq) for i in range(nq))
+    Hc = np.stack([site_op(i, "z", nq) for i in range(nq)])
+    u = rng.normal(0, 0.5, (nq, N))
+    V = np.diag(np.exp(1j * rng.uniform(0, 6.3, 2 ** nq)))
+    r = oracle.grape_ref(Problem(H0, Hc, u, dt, V))
+    spread = np.max(np.abs(r["grad"] - r["grad"][:, :1]))
+    assert spread < 1e-14
+    assert np.max(np.abs(r["grad"])) > 1e-4
+
+
+def test_stationary_point_at_reached_target():
+    p = make_config(2, N=30)
+    XN = oracle.fidelity_ref(p)["XN"]
+    r = oracle.grape_ref(p.with_target(XN))
+    assert abs(r["F"] - 1) < 1e-13
+    assert np.max(np.abs(r["grad"])) < 1e-12
+
+
+@pytest.mark.parametrize("d,degenerate", [(4, False), (8, False), (16, True)])
+def test_frechet_matches_scipy_expm_frechet(d, degenerate):
+    rng = np.random.default_rng(d)
+    if degenerate:
+        H = heisenberg_drift([1.0, 1.0, 1.0], [0.0] * 4)   # large degenerate subspaces
+    else:
+        Z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        H = (Z + Z.conj().T) / 2
+    E = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    dt = 0.3
+    lam, Q = np.linalg.eigh(H)
+    L = oracle.frechet_dk(lam, Q, dt, E)
+    _, Lref = sla.expm_frechet(-1j * dt * H, E)
+    assert np.max(np.abs(L - Lref)) < 1e-12 * max(1.0, np.max(np.abs(Lref)))
+
+
+def test_frechet_commuting_direction_and_linearity():
+    rng = np.random.default_rng(3)
+    Z = rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))
+    H = (Z + Z.conj().T) / 2
+    dt = 0.2
+    A = -1j * dt * H
+    lam, Q = np.linalg.eigh(H)
+    E = A @ A + 2 * A + 0.5 * np.eye(8)               # commutes with A
+    L = oracle.frechet_dk(lam, Q, dt, E)
+    assert np.max(np.abs(L - E @ sla.expm(A))) < 1e-13
+    E1 = rng.normal(size=(8, 8)) + 0j
+    E2 = 1j * rng.normal(size=(8, 8))
+    lin = oracle.frechet_dk(lam, Q, dt, 2 * E1 - 3 * E2)
+    assert np.max(np.abs(lin - 2 * oracle.frechet_dk(lam, Q, dt, E1)
+                         + 3 * oracle.frechet_dk(lam, Q, dt, E2))) < 1e-13
+
+
+def test_frechet_central_difference_of_expm():
+    rng = np.random.default_rng(9)
+    Z = rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6))
+    H = (Z + Z.conj().T) / 2
+    Z2 = rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6))
+    Hj = (Z2 + Z2.conj().T) / 2
+    dt, h = 0.1, 1e-5
+    lam, Q = np.linalg.eigh(H)
+    L = oracle.frechet_dk(lam, Q, dt, -1j * dt * Hj)
+    fd = (oracle.expm_herm(H + h * Hj, dt)[0] - oracle.expm_herm(H - h * Hj, dt)[0]) / (2 * h)
+    assert np.max(np.abs(L - fd)) < 1e-9
+
+
+def _block_exponent_gradient(p):
+    """Independent gradient: Van Loan block exponent with scipy's Pade expm,
+    L(A, E) = top-right block of expm([[A, E], [0, A]])."""
+    d, m, N = p.d, p.m, p.N
+    Us = [sla.expm(-1j * p.dt * (p.H0 + np.einsum("j,jab->ab", p.u[:, k], p.Hc))) for k in range(N)]
+    Xs = [np.eye(d)]
+    for U in Us:
+        Xs.append(U @ Xs[-1])
+    Bs = [None] * (N + 1)
+    Bs[N] = p.V
+    for k in range(N - 1, -1, -1):
+        Bs[k] = Us[k].conj().T @ Bs[k + 1]
+    g = np.trace(p.V.conj().T @ Xs[-1])
+    grad = np.zeros((m, N))
+    for k in range(N):
+        A = -1j * p.dt * (p.H0 + np.einsum("j,jab->ab", p.u[:, k], p.Hc))
+        for j in range(m):
+            M = np.zeros((2 * d, 2 * d), dtype=complex)
+            M[:d, :d] = A
+            M[d:, d:] = A
+            M[:d, d:] = -1j * p.dt * p.Hc[j]
+            L = sla.expm(M)[:d, d:]
+            dg = np.trace(Bs[k + 1].conj().T @ L @ Xs[k])
+            grad[j, k] = 2 / d ** 2 * (np.conj(g) * dg).real
+    return grad
+
+
+@pytest.mark.parametrize("cfg,N", [(1, 20), (2, 6)])
+def test_gradient_matches_block_exponent_gradient(cfg, N):
+    p = make_config(cfg, N=N)
+    r = oracle.grape_ref(p)
+    ref = _block_exponent_gradient(p)
+    assert np.max(np.abs(r["grad"] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("cfg,N,nent", [(1, 100, 20), (2, 40, 16), (3, 12, 8)])
+def test_gradient_central_finite_differences(cfg, N, nent):
+    """Central differences of the oracle's F with h = 1e-6 on random entries."""
+    p = make_config(cfg, N=N)
+    r = oracle.grape_ref(p)
+    rng = np.random.default_rng(100 + cfg)
+    flat = rng.choice(p.m * p.N, size=nent, replace=False)
+    gmax = np.max(np.abs(r["grad"]))
+    h = 1e-6
+    for f in flat:
+        j, k = divmod(int(f), p.N)
+        up, dn = p.u.copy(), p.u.copy()
+        up[j, k] += h
+        dn[j, k] -= h
+        fd = (oracle.fidelity_ref(p.with_u(up))["F"] - oracle.fidelity_ref(p.with_u(dn))["F"]) / (2 * h)
+        assert abs(fd - r["grad"][j, k]) <= 1e-4 * max(abs(r["grad"][j, k]), 0.1 * gmax)
