@@ -1,0 +1,135 @@
+/*
+ * libqoc: piecewise-constant quantum optimal control (GRAPE) on AMD MI355X.
+ *
+ * The problem (GRAPE, Khaneja et al., J. Magn. Reson. 172 (2005); hbar = 1):
+ *
+ *   H_k  = H0 + sum_{j<m} u[j*N + k] * Hc[j]         slice Hamiltonian, k = 0..N-1
+ *   U_k  = exp(-i * dt * H_k)                          slice propagator
+ *   X_N  = U_{N-1} ... U_1 U_0                         slice 0 acts first
+ *   g    = Tr(V^dag X_N),   F = |g|^2 / d^2            phase-insensitive fidelity
+ *   grad[j*N + k] = dF / du[j*N + k]                   exact derivative of the
+ *                                                      piecewise-constant model
+ *
+ * Matrices are d x d, row-major, complex interleaved (re, im) in double
+ * precision (qoc_z).  H0 and every Hc[j] must be Hermitian and V unitary.
+ * u and grad are m x N row-major doubles.  Supported sizes: 1 <= d <= 128,
+ * m >= 1, N >= 1.
+ *
+ * Ownership: the caller owns every buffer; the library keeps no pointer to
+ * caller memory after a call returns.  Host entry points (no _dev suffix) take
+ * host pointers, allocate and free their own device memory, and return when
+ * the results are in the host buffers.  _dev entry points take device pointers
+ * and a caller-provided device workspace, enqueue all work on opt->stream
+ * (NULL: the default stream) and return without waiting; outputs are valid
+ * once that stream has completed.
+ *
+ * Errors: every entry point returns QOC_OK (0) or a negative qoc_status.  On
+ * error nothing has been launched and the outputs are untouched;
+ * qoc_last_error() then returns a message for the calling thread.  No entry
+ * point aborts or throws across this boundary.
+ */
+#ifndef QOC_H
+#define QOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} qoc_z; /* complex128, interleaved */
+
+typedef enum {
+  QOC_OK = 0,
+  QOC_ERR_ARG = -1,           /* bad size, NULL pointer, dt <= 0, workspace too small */
+  QOC_ERR_NOT_HERMITIAN = -2, /* validate != 0 and H0 or some Hc[j] is not Hermitian */
+  QOC_ERR_NONFINITE = -3,     /* validate != 0 and an input holds NaN or Inf */
+  QOC_ERR_OOM = -4,           /* device allocation failed (host entry points) */
+  QOC_ERR_DEVICE = -5,        /* a HIP runtime call or kernel launch failed */
+  QOC_ERR_UNSUPPORTED = -6    /* d > 128 or an unknown precision */
+} qoc_status;
+
+typedef enum {
+  QOC_FP64 = 0,  /* complex128 GEMMs on FP64 MFMA */
+  QOC_FP32 = 1,  /* complex64 GEMMs on FP32 MFMA; norms, traces and inner products in FP64 */
+  QOC_BF16X3 = 2 /* reserved: split-BF16 products with FP32 accumulation */
+} qoc_precision;
+
+typedef struct {
+  int32_t precision;      /* qoc_precision; default QOC_FP64 */
+  int32_t validate;       /* nonzero: host entry points check Hermiticity and finiteness */
+  uint64_t hbm_budget;    /* reserved for checkpointing; 0 = no limit */
+  double reunitarise_tol; /* reserved; < 0 disables */
+  void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
+  int32_t chunk;          /* slices per scan chunk; 0 = ceil(sqrt(N)) */
+  int32_t reserved;
+} qoc_options; /* pass NULL for all defaults */
+
+/* Fill *opt with the defaults listed above. */
+void qoc_default_options(qoc_options* opt);
+
+/*
+ * Total propagator X_N = U_{N-1} ... U_0 (defined above).
+ * H0: d*d, Hc: m*d*d (control j at Hc + j*d*d), u: m*N, U_total: d*d output.
+ */
+int qoc_propagate(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                  double dt, qoc_z* U_total, const qoc_options* opt);
+
+/* Fidelity F = |Tr(V^dag X_N)|^2 / d^2 against the d*d target V. */
+int qoc_fidelity(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                 double dt, const qoc_z* V, double* F, const qoc_options* opt);
+
+/* F and its exact gradient grad[j*N + k] = dF/du[j*N + k] (m*N output). */
+int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                 double dt, const qoc_z* V, double* F, double* grad, const qoc_options* opt);
+
+/*
+ * Batched device entry points: B independent problems with the same d, m, N
+ * and dt, stored back to back in device memory:
+ *   H0 [B][d][d], Hc [B][m][d][d], u [B][m][N], V [B][d][d]  (qoc_z / double),
+ *   F [B], grad [B][m][N], U_total [B][d][d].
+ * workspace must hold qoc_workspace_size(...) bytes of device memory, 256-byte
+ * aligned; its contents need no initialisation and are clobbered.  Calls that
+ * share a workspace must be ordered on one stream.
+ */
+size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk);
+
+int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                      const void* u, double dt, void* U_total, void* workspace,
+                      size_t ws_bytes, const qoc_options* opt);
+
+int qoc_fidelity_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                     const void* u, double dt, const void* V, void* F, void* workspace,
+                     size_t ws_bytes, const qoc_options* opt);
+
+int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                     const void* u, double dt, const void* V, void* F, void* grad,
+                     void* workspace, size_t ws_bytes, const qoc_options* opt);
+
+/*
+ * Scaling exponent and Taylor degrees the kernels use for each slice of one
+ * problem (host pointers): plan[3*k + 0] = s, plan[3*k + 1] = q (degree of
+ * the exp series), plan[3*k + 2] = qb (degree of the Frechet block series).
+ * theta_k = dt (|H0|_1 + sum_j |u[j*N + k]| |Hc[j]|_1) bounds |dt H_k|_1;
+ * q and qb are the least degrees whose Taylor remainder bounds at
+ * r = theta_k / 2^s are at most the unit roundoff of the precision, and s
+ * minimises the number of complex matrix products (with_gradient selects the
+ * count of the gradient path).  Returns QOC_OK or QOC_ERR_ARG.
+ */
+int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                   double dt, int precision, int with_gradient, int32_t* plan);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* qoc_last_error(void);
+
+/* Library version string. */
+const char* qoc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QOC_H */

@@ -1,0 +1,351 @@
+// libqoc C ABI: argument checks, workspace layout, descriptor upload and the
+// launch sequence of the GRAPE hot path (see include/qoc.h for the contract).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "qoc.h"
+#include "qoc_internal.hpp"
+#include "qoc_plan.hpp"
+
+using qoc::Launch;
+using qoc::ProbDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int padded_dim(int d) {
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  return 128;
+}
+
+size_t elem_size(int precision) { return precision == QOC_FP64 ? 8 : 4; }
+
+// Byte offsets of one problem's workspace regions, and the total size.
+struct Layout {
+  int D, L, P;
+  size_t desc_bytes;  // descriptor table at the start of the workspace
+  size_t Hint, Vint, norms, sq, delta, xprev, bloc, tf, tb, cf, cb, mc, small;
+  size_t per_prob;
+  size_t total;
+};
+
+Layout make_layout(int B, int d, int m, int N, int precision, int chunk) {
+  Layout Lo;
+  Lo.D = padded_dim(d);
+  Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
+  if (Lo.L < 1) Lo.L = 1;
+  Lo.P = (N + Lo.L - 1) / Lo.L;
+  const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
+  size_t o = 0;
+  Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
+  Lo.Vint = o; o = align_up(o + mat);
+  Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
+  Lo.sq = o; o = align_up(o + (size_t)N * 4);
+  Lo.delta = o; o = align_up(o + (size_t)N * mat);
+  Lo.xprev = o; o = align_up(o + (size_t)N * mat);
+  Lo.bloc = o; o = align_up(o + (size_t)N * mat);
+  Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.tb = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.cb = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.mc = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.small = o; o = align_up(o + 128);
+  Lo.per_prob = o;
+  Lo.desc_bytes = align_up((size_t)B * sizeof(ProbDesc));
+  Lo.total = Lo.desc_bytes + (size_t)B * Lo.per_prob;
+  return Lo;
+}
+
+int check_dims(int B, int d, int m, int N, int precision) {
+  if (B < 1) return fail(QOC_ERR_ARG, "batch size B = %d must be >= 1", B);
+  if (d < 1 || m < 1 || N < 1) return fail(QOC_ERR_ARG, "need d, m, N >= 1 (got d=%d m=%d N=%d)", d, m, N);
+  if (d > 128) return fail(QOC_ERR_UNSUPPORTED, "d = %d exceeds the supported maximum 128", d);
+  if (d > 64) return fail(QOC_ERR_UNSUPPORTED, "d = %d: dimensions above 64 are not built into this library", d);
+  if (precision != QOC_FP64 && precision != QOC_FP32)
+    return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
+  return QOC_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// |H - H^dag|_max <= 1e-12 max(1, |H|_max)
+bool hermitian(const qoc_z* H, int d) {
+  double hmax = 0, dmax = 0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      const qoc_z x = H[a * d + b], y = H[b * d + a];
+      hmax = std::max(hmax, std::max(fabs(x.re), fabs(x.im)));
+      dmax = std::max(dmax, std::max(fabs(x.re - y.re), fabs(x.im + y.im)));
+    }
+  return dmax <= 1e-12 * std::max(1.0, hmax);
+}
+
+int validate_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, const qoc_z* V) {
+  const size_t dd = (size_t)d * d;
+  if (!finite_all(&H0->re, 2 * dd) || !finite_all(&Hc->re, 2 * dd * m) || !finite_all(u, (size_t)m * N) ||
+      (V && !finite_all(&V->re, 2 * dd)))
+    return fail(QOC_ERR_NONFINITE, "an input holds NaN or Inf");
+  if (!hermitian(H0, d)) return fail(QOC_ERR_NOT_HERMITIAN, "H0 is not Hermitian");
+  for (int j = 0; j < m; ++j)
+    if (!hermitian(Hc + (size_t)j * dd, d)) return fail(QOC_ERR_NOT_HERMITIAN, "Hc[%d] is not Hermitian", j);
+  return QOC_OK;
+}
+
+qoc_options defaults() {
+  qoc_options o;
+  qoc_default_options(&o);
+  return o;
+}
+
+// Enqueue the path for a uniform batch whose inputs and outputs are in
+// device memory.  flags: qoc::RUN_* bits.
+int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt, const void* V,
+            void* F, void* grad, void* XN, void* ws, size_t ws_bytes, const qoc_options* opt_in, int flags) {
+  const qoc_options opt = opt_in ? *opt_in : defaults();
+  int rc = check_dims(B, d, m, N, opt.precision);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(QOC_ERR_ARG, "dt must be finite and > 0");
+  if (!H0 || !Hc || !u) return fail(QOC_ERR_ARG, "H0, Hc and u must be non-null");
+  if ((flags & qoc::RUN_FID) && (!V || !F)) return fail(QOC_ERR_ARG, "V and F must be non-null");
+  if ((flags & qoc::RUN_GRAD) && !grad) return fail(QOC_ERR_ARG, "grad must be non-null");
+  if (!ws) return fail(QOC_ERR_ARG, "workspace must be non-null");
+  if (((uintptr_t)ws) % kAlign) return fail(QOC_ERR_ARG, "workspace must be 256-byte aligned");
+  const Layout Lo = make_layout(B, d, m, N, opt.precision, opt.chunk);
+  if (ws_bytes < Lo.total)
+    return fail(QOC_ERR_ARG, "workspace holds %zu bytes, %zu needed", ws_bytes, Lo.total);
+
+  char* base = static_cast<char*>(ws);
+  std::vector<ProbDesc> descs(B);
+  const size_t dd = (size_t)d * d;
+  for (int b = 0; b < B; ++b) {
+    char* pb = base + Lo.desc_bytes + (size_t)b * Lo.per_prob;
+    ProbDesc& P = descs[b];
+    memset(&P, 0, sizeof P);
+    P.d = d;
+    P.D = Lo.D;
+    P.m = m;
+    P.N = N;
+    P.L = Lo.L;
+    P.P = Lo.P;
+    P.flags = flags;
+    P.dt = dt;
+    P.H0z = static_cast<const double*>(H0) + 2 * dd * b;
+    P.Hcz = static_cast<const double*>(Hc) + 2 * dd * m * b;
+    P.u = static_cast<const double*>(u) + (size_t)m * N * b;
+    P.Vz = V ? static_cast<const double*>(V) + 2 * dd * b : nullptr;
+    P.grad = grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr;
+    P.XN = XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr;
+    P.Hint = pb + Lo.Hint;
+    P.Vint = V ? pb + Lo.Vint : nullptr;
+    P.norms = reinterpret_cast<double*>(pb + Lo.norms);
+    P.sq = reinterpret_cast<int*>(pb + Lo.sq);
+    P.delta = pb + Lo.delta;
+    P.xprev = pb + Lo.xprev;
+    P.bloc = pb + Lo.bloc;
+    P.tf = pb + Lo.tf;
+    P.tb = pb + Lo.tb;
+    P.cf = pb + Lo.cf;
+    P.cb = pb + Lo.cb;
+    P.mc = pb + Lo.mc;
+    double* small = reinterpret_cast<double*>(pb + Lo.small);
+    P.g = small;                                           // 2 doubles
+    P.F = F ? static_cast<double*>(F) + b : small + 2;     // 1 double
+    P.diag = small + 4;                                    // 4 doubles
+  }
+  hipStream_t st = static_cast<hipStream_t>(opt.stream);
+  hipError_t e = hipMemcpyAsync(base, descs.data(), (size_t)B * sizeof(ProbDesc), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "descriptor upload: %s", hipGetErrorString(e));
+
+  Launch L;
+  L.descs = reinterpret_cast<const ProbDesc*>(base);
+  L.nprob = B;
+  L.uniformN = N;
+  L.uniformP = Lo.P;
+  L.slice_start = nullptr;
+  L.chunk_start = nullptr;
+  L.total_slices = B * N;
+  L.total_chunks = B * Lo.P;
+  L.max_m = m;
+  L.flags = flags;
+  L.stream = st;
+  e = qoc::launch_path(opt.precision, Lo.D, L);
+  if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+  return QOC_OK;
+}
+
+// Device buffers of a host call, freed on scope exit.
+struct DevBufs {
+  std::vector<void*> ptrs;
+  ~DevBufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  void* alloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, n ? n : 1) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return p;
+  }
+};
+
+int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt, const qoc_z* V,
+             double* F, double* grad, qoc_z* XN, const qoc_options* opt_in, int flags) {
+  const qoc_options opt = opt_in ? *opt_in : defaults();
+  int rc = check_dims(1, d, m, N, opt.precision);
+  if (rc) return rc;
+  if (!H0 || !Hc || !u) return fail(QOC_ERR_ARG, "H0, Hc and u must be non-null");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(QOC_ERR_ARG, "dt must be finite and > 0");
+  if ((flags & qoc::RUN_FID) && (!V || !F)) return fail(QOC_ERR_ARG, "V and F must be non-null");
+  if ((flags & qoc::RUN_GRAD) && !grad) return fail(QOC_ERR_ARG, "grad must be non-null");
+  if (!(flags & qoc::RUN_FID) && !XN) return fail(QOC_ERR_ARG, "U_total must be non-null");
+  if (opt.validate) {
+    rc = validate_host(d, m, N, H0, Hc, u, V);
+    if (rc) return rc;
+  }
+  const size_t dd = (size_t)d * d;
+  const size_t ws_bytes = make_layout(1, d, m, N, opt.precision, opt.chunk).total;
+  DevBufs bufs;
+  void* dH0 = bufs.alloc(dd * 16);
+  void* dHc = bufs.alloc(dd * 16 * m);
+  void* du = bufs.alloc((size_t)m * N * 8);
+  void* dV = V ? bufs.alloc(dd * 16) : nullptr;
+  void* dF = bufs.alloc(8);
+  void* dgrad = grad ? bufs.alloc((size_t)m * N * 8) : nullptr;
+  void* dXN = XN ? bufs.alloc(dd * 16) : nullptr;
+  void* dws = bufs.alloc(ws_bytes);
+  if (!dH0 || !dHc || !du || (V && !dV) || !dF || (grad && !dgrad) || (XN && !dXN) || !dws)
+    return fail(QOC_ERR_OOM, "device allocation of %zu workspace bytes failed", ws_bytes);
+  hipStream_t st = static_cast<hipStream_t>(opt.stream);
+  hipError_t e = hipSuccess;
+  e = e ? e : hipMemcpyAsync(dH0, H0, dd * 16, hipMemcpyHostToDevice, st);
+  e = e ? e : hipMemcpyAsync(dHc, Hc, dd * 16 * m, hipMemcpyHostToDevice, st);
+  e = e ? e : hipMemcpyAsync(du, u, (size_t)m * N * 8, hipMemcpyHostToDevice, st);
+  if (V) e = e ? e : hipMemcpyAsync(dV, V, dd * 16, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
+  qoc_options o2 = opt;
+  rc = run_dev(1, d, m, N, dH0, dHc, du, dt, dV, dF, dgrad, dXN, dws, ws_bytes, &o2, flags);
+  if (rc) return rc;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "execution: %s", hipGetErrorString(e));
+  if (F) e = e ? e : hipMemcpy(F, dF, 8, hipMemcpyDeviceToHost);
+  if (grad) e = e ? e : hipMemcpy(grad, dgrad, (size_t)m * N * 8, hipMemcpyDeviceToHost);
+  if (XN) e = e ? e : hipMemcpy(XN, dXN, dd * 16, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "download: %s", hipGetErrorString(e));
+  return QOC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qoc_default_options(qoc_options* opt) {
+  if (!opt) return;
+  memset(opt, 0, sizeof *opt);
+  opt->precision = QOC_FP64;
+  opt->validate = 0;
+  opt->hbm_budget = 0;
+  opt->reunitarise_tol = -1.0;
+  opt->stream = nullptr;
+  opt->chunk = 0;
+}
+
+int qoc_propagate(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,
+                  qoc_z* U_total, const qoc_options* opt) {
+  return run_host(d, m, N, H0, Hc, u, dt, nullptr, nullptr, nullptr, U_total, opt, 0);
+}
+
+int qoc_fidelity(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,
+                 const qoc_z* V, double* F, const qoc_options* opt) {
+  return run_host(d, m, N, H0, Hc, u, dt, V, F, nullptr, nullptr, opt, qoc::RUN_FID);
+}
+
+int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,
+                 const qoc_z* V, double* F, double* grad, const qoc_options* opt) {
+  return run_host(d, m, N, H0, Hc, u, dt, V, F, grad, nullptr, opt,
+                  qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
+}
+
+size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk) {
+  if (check_dims(B, d, m, N, precision)) return 0;
+  return make_layout(B, d, m, N, precision, chunk).total;
+}
+
+int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
+                      void* U_total, void* workspace, size_t ws_bytes, const qoc_options* opt) {
+  if (!U_total) return fail(QOC_ERR_ARG, "U_total must be non-null");
+  return run_dev(B, d, m, N, H0, Hc, u, dt, nullptr, nullptr, nullptr, U_total, workspace, ws_bytes, opt, 0);
+}
+
+int qoc_fidelity_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
+                     const void* V, void* F, void* workspace, size_t ws_bytes, const qoc_options* opt) {
+  return run_dev(B, d, m, N, H0, Hc, u, dt, V, F, nullptr, nullptr, workspace, ws_bytes, opt, qoc::RUN_FID);
+}
+
+int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
+                     const void* V, void* F, void* grad, void* workspace, size_t ws_bytes,
+                     const qoc_options* opt) {
+  return run_dev(B, d, m, N, H0, Hc, u, dt, V, F, grad, nullptr, workspace, ws_bytes, opt,
+                 qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
+}
+
+int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,
+                   int precision, int with_gradient, int32_t* plan) {
+  if (d < 1 || m < 1 || N < 1 || !H0 || !Hc || !u || !plan || !(dt > 0))
+    return fail(QOC_ERR_ARG, "invalid arguments to qoc_slice_plan");
+  if (precision != QOC_FP64 && precision != QOC_FP32)
+    return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
+  const double ur = precision == QOC_FP64 ? 0x1p-53 : 0x1p-24;
+  auto norm1 = [d](const qoc_z* H) {
+    double best = 0;
+    for (int b = 0; b < d; ++b) {
+      double s = 0;
+      for (int a = 0; a < d; ++a) s += sqrt(fma(H[a * d + b].re, H[a * d + b].re, H[a * d + b].im * H[a * d + b].im));
+      best = std::max(best, s);
+    }
+    return best;
+  };
+  std::vector<double> nrm(m + 1);
+  nrm[0] = norm1(H0);
+  for (int j = 0; j < m; ++j) nrm[j + 1] = norm1(Hc + (size_t)j * d * d);
+  for (int k = 0; k < N; ++k) {
+    double th = nrm[0];
+    for (int j = 0; j < m; ++j) th = fma(fabs(u[(size_t)j * N + k]), nrm[j + 1], th);
+    th *= dt;
+    qoc::SlicePlan p = qoc::choose_plan(th, ur, with_gradient != 0);
+    plan[3 * k] = p.s;
+    plan[3 * k + 1] = p.q;
+    plan[3 * k + 2] = p.qb;
+  }
+  return QOC_OK;
+}
+
+const char* qoc_last_error(void) { return g_err.c_str(); }
+
+const char* qoc_version(void) { return "libqoc 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,325 @@
+// Device building blocks for the GRAPE kernels on gfx950 (CDNA4).
+//
+// A D x D complex matrix is processed by D/16 wavefronts; wavefront w owns the
+// 16-column panel [16w, 16w + 16).  A panel is held in registers in the output
+// ("C") layout of the 16x16x4 MFMA: for row block rb (16 rows) each lane holds
+// four values per real plane.  Lane l = 16 g + c16 holds column 16w + c16 and
+// rows 16 rb + rowmap(r, g), r = 0..3, where rowmap is the accumulator layout
+// of the instruction (FP32: 4g + r; FP64: 4r + g).
+//
+// A panel in that layout is fed straight back as the B operand of the next
+// MFMA: register r of row block rb supplies K index g (= lane / 16), which
+// stands for matrix row 16 rb + rowmap(r, g).  The A operand is read from LDS
+// with the matching permutation of its columns, so chained products
+// (Horner steps, scan steps) keep their state in registers and only the
+// left factor is staged in LDS.  Complex products use four real MFMAs:
+//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+//
+// LDS matrices are row-major with separate real and imaginary planes, a row
+// stride of D + pad elements (16 bytes of padding) and, within each 16-column
+// block, the column permutation perm() under which the four A values a lane
+// needs for one row block are contiguous (one 16-byte read for FP32, two for
+// FP64).
+//
+// Stored matrices ("PF" layout) keep the register order of a panel so that a
+// wavefront loads or stores its panel with fully coalesced 16-byte accesses:
+//   index(w, plane, reg, lane) = ((w*2 + plane) * (D/4/G) + reg/G) * 64 * G + lane * G + reg % G
+// with reg = 4 rb + r and G = 16 / sizeof(T) elements per 16-byte access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qoc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Prec;
+
+template <>
+struct Prec<float> {
+  using v4 = f4;
+  static constexpr int PAD = 4;
+  __device__ static __forceinline__ int rowmap(int r, int g) { return 4 * g + r; }
+  __device__ static __forceinline__ int perm(int c) { return c; }
+  __device__ static __forceinline__ v4 mfma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ v4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
+  __device__ static __forceinline__ void st4(float* p, v4 v) { *reinterpret_cast<f4*>(p) = v; }
+};
+
+template <>
+struct Prec<double> {
+  using v4 = d4;
+  static constexpr int PAD = 2;
+  __device__ static __forceinline__ int rowmap(int r, int g) { return 4 * r + g; }
+  __device__ static __forceinline__ int perm(int c) { return 4 * (c & 3) + (c >> 2); }
+  __device__ static __forceinline__ v4 mfma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ v4 ld4(const double* p) {
+    d2 lo = *reinterpret_cast<const d2*>(p);
+    d2 hi = *reinterpret_cast<const d2*>(p + 2);
+    v4 v;
+    v.x = lo.x; v.y = lo.y; v.z = hi.x; v.w = hi.y;
+    return v;
+  }
+  __device__ static __forceinline__ void st4(double* p, v4 v) {
+    d2 lo, hi;
+    lo.x = v.x; lo.y = v.y; hi.x = v.z; hi.y = v.w;
+    *reinterpret_cast<d2*>(p) = lo;
+    *reinterpret_cast<d2*>(p + 2) = hi;
+  }
+};
+
+// Elements of one stored matrix (both planes).
+template <typename T, int D>
+struct Mat {
+  static constexpr int SD = D + Prec<T>::PAD;  // LDS row stride
+  static constexpr int LDS_ELEMS = 2 * D * SD;  // one LDS matrix, both planes
+  static constexpr int ELEMS = 2 * D * D;       // one stored matrix
+  static constexpr int RB = D / 16;             // row blocks per panel
+  static constexpr int NW = D / 16;             // wavefronts per matrix
+  static constexpr int NT = 64 * NW;            // threads per matrix
+};
+
+template <typename T, int D>
+struct Panel {
+  using v4 = typename Prec<T>::v4;
+  v4 re[D / 16];
+  v4 im[D / 16];
+};
+
+struct Lane {
+  int w, g, c16, lane;
+  __device__ __forceinline__ Lane() {
+    lane = threadIdx.x & 63;
+    w = threadIdx.x >> 6;
+    g = lane >> 4;
+    c16 = lane & 15;
+  }
+};
+
+// LDS offset of logical element (row, col).
+template <typename T, int D>
+__device__ __forceinline__ int lds_off(int row, int col) {
+  return row * Mat<T, D>::SD + (col & ~15) + Prec<T>::perm(col & 15);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_zero(Panel<T, D>& P) {
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+    P.re[rb] = 0;
+    P.im[rb] = 0;
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_identity(Panel<T, D>& P, const Lane& L) {
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P.re[rb][r] = (rb == L.w && Prec<T>::rowmap(r, L.g) == L.c16) ? T(1) : T(0);
+    P.im[rb] = 0;
+  }
+}
+
+// P += a * I
+template <typename T, int D>
+__device__ __forceinline__ void panel_add_identity(Panel<T, D>& P, const Lane& L, T a) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (Prec<T>::rowmap(r, L.g) == L.c16) {
+#pragma unroll
+      for (int rb = 0; rb < D / 16; ++rb)
+        if (rb == L.w) P.re[rb][r] += a;
+    }
+}
+
+// Y = a * X + b * Y  (elementwise on panels)
+template <typename T, int D>
+__device__ __forceinline__ void panel_axpby(Panel<T, D>& Y, T a, const Panel<T, D>& X, T b) {
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+    Y.re[rb] = a * X.re[rb] + b * Y.re[rb];
+    Y.im[rb] = a * X.im[rb] + b * Y.im[rb];
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_scale(Panel<T, D>& Y, T a) {
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+    Y.re[rb] *= a;
+    Y.im[rb] *= a;
+  }
+}
+
+// ---------------------------------------------------------------- LDS <-> panel
+
+// Panel of the matrix stored in LDS (same orientation).
+template <typename T, int D>
+__device__ __forceinline__ void panel_from_lds(Panel<T, D>& P, const T* lds, const Lane& L) {
+  const T* im = lds + D * Mat<T, D>::SD;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int off = lds_off<T, D>(16 * rb + Prec<T>::rowmap(r, L.g), 16 * L.w + L.c16);
+      P.re[rb][r] = lds[off];
+      P.im[rb][r] = im[off];
+    }
+}
+
+// Panel of the conjugate transpose of the matrix stored in LDS.  Element
+// (row, col) of M^dag is conj(M[col][row]); the four values of one row block
+// sit contiguously in LDS row 16w + c16, so each plane takes one vector read.
+template <typename T, int D>
+__device__ __forceinline__ void panel_from_lds_ct(Panel<T, D>& P, const T* lds, const Lane& L) {
+  const T* im = lds + D * Mat<T, D>::SD;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+    int off = (16 * L.w + L.c16) * Mat<T, D>::SD + 16 * rb + 4 * L.g;
+    P.re[rb] = Prec<T>::ld4(lds + off);
+    P.im[rb] = -Prec<T>::ld4(im + off);
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_to_lds(T* lds, const Panel<T, D>& P, const Lane& L) {
+  T* im = lds + D * Mat<T, D>::SD;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int off = lds_off<T, D>(16 * rb + Prec<T>::rowmap(r, L.g), 16 * L.w + L.c16);
+      lds[off] = P.re[rb][r];
+      im[off] = P.im[rb][r];
+    }
+}
+
+// Store the conjugate transpose of the panel's matrix into LDS.
+template <typename T, int D>
+__device__ __forceinline__ void panel_to_lds_ct(T* lds, const Panel<T, D>& P, const Lane& L) {
+  T* im = lds + D * Mat<T, D>::SD;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb) {
+    int off = (16 * L.w + L.c16) * Mat<T, D>::SD + 16 * rb + 4 * L.g;
+    Prec<T>::st4(lds + off, P.re[rb]);
+    Prec<T>::st4(im + off, -P.im[rb]);
+  }
+}
+
+// ---------------------------------------------------------------- MFMA product
+
+// acc = A * P (zero_acc) or acc += A * P, with A a D x D matrix in LDS and P a
+// panel.  Each wavefront computes its own 16 output columns; no barrier inside.
+// The product runs over (k block, output row block) steps; the A fragment of
+// the next step is read from LDS while the 16 MFMAs of the current step issue,
+// and scheduling barriers keep the compiler from hoisting every LDS read to
+// the top (which would cost one register set per step).
+template <typename T, int D>
+__device__ __forceinline__ void cgemm(Panel<T, D>& acc, const T* A, const Panel<T, D>& P, const Lane& L,
+                                      bool zero_acc) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int RB = D / 16;
+  constexpr int SD = Mat<T, D>::SD;
+  constexpr int STEPS = RB * RB;
+  const T* Ai = A + D * SD;
+  const int base = L.c16 * SD + 4 * L.g;
+  __builtin_amdgcn_sched_barrier(0);
+  if (zero_acc) panel_zero(acc);
+  v4 ar[2], ai[2];
+  ar[0] = Prec<T>::ld4(A + base);
+  ai[0] = Prec<T>::ld4(Ai + base);
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st) {
+    const int kb = st / RB, mb = st % RB;
+    const int cur = st & 1;
+    if (st + 1 < STEPS) {
+      const int kn = (st + 1) / RB, mn = (st + 1) % RB;
+      const int off = base + 16 * mn * SD + 16 * kn;
+      ar[cur ^ 1] = Prec<T>::ld4(A + off);
+      ai[cur ^ 1] = Prec<T>::ld4(Ai + off);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T br = P.re[kb][r];
+      const T bi = P.im[kb][r];
+      acc.re[mb] = Prec<T>::mfma(ar[cur][r], br, acc.re[mb]);
+      acc.im[mb] = Prec<T>::mfma(ar[cur][r], bi, acc.im[mb]);
+      acc.re[mb] = Prec<T>::mfma(-ai[cur][r], bi, acc.re[mb]);
+      acc.im[mb] = Prec<T>::mfma(ai[cur][r], br, acc.im[mb]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// ---------------------------------------------------------------- stored (PF) matrices
+
+template <typename T, int D>
+__device__ __forceinline__ int pf_index(int w, int plane, int reg, int lane) {
+  constexpr int G = 16 / sizeof(T);
+  return ((w * 2 + plane) * (D / 4 / G) + reg / G) * 64 * G + lane * G + reg % G;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_load(Panel<T, D>& P, const T* M, const Lane& L) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) {
+      P.re[rb] = *reinterpret_cast<const f4*>(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane));
+      P.im[rb] = *reinterpret_cast<const f4*>(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane));
+    }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) {
+#pragma unroll
+      for (int plane = 0; plane < 2; ++plane) {
+        d2 a = *reinterpret_cast<const d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane));
+        d2 b = *reinterpret_cast<const d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane));
+        d4 v;
+        v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+        if (plane == 0) P.re[rb] = v; else P.im[rb] = v;
+      }
+    }
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void panel_store(T* M, const Panel<T, D>& P, const Lane& L) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) {
+      *reinterpret_cast<f4*>(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane)) = P.re[rb];
+      *reinterpret_cast<f4*>(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane)) = P.im[rb];
+    }
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) {
+#pragma unroll
+      for (int plane = 0; plane < 2; ++plane) {
+        d4 v = plane == 0 ? P.re[rb] : P.im[rb];
+        d2 a, b;
+        a.x = v.x; a.y = v.y; b.x = v.z; b.y = v.w;
+        *reinterpret_cast<d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane)) = a;
+        *reinterpret_cast<d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane)) = b;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace qoc

@@ -1,0 +1,83 @@
+// Choice of the scaling exponent s and the Taylor degrees (q for exp, qb for
+// its Frechet block) of one slice, shared by the plan kernel and the host.
+//
+// theta = dt (|H0|_1 + sum_j |u[j][k]| |Hc[j]|_1) bounds |A_k|_1 by the
+// triangle inequality (A_k = -i dt H_k), and |A^n| <= |A|^n in the 1-norm.
+// With r = theta / 2^s:
+//  * exp: the Taylor remainder after degree q is at most
+//    r^(q+1)/(q+1)! * 1/(1 - r/(q+2)) (geometric bound on the tail ratios);
+//    q is the least degree for which this is at most the unit roundoff ur.
+//  * Frechet block exp([[X, E], [0, X]]): its top-right block is linear in E
+//    and the degree-n term of the series contributes n X^(n-1)-type products,
+//    so the remainder after degree qb is at most
+//    |E| r^qb/qb! * 1/(1 - r/(qb+1)); qb (>= 2) is the least degree for which
+//    the factor of |E| is at most ur.
+// Among s in [s0, s0 + 6], s0 = least s >= 0 with r <= 1, the value that
+// minimises the number of complex d x d products of the path is taken:
+//    exp:       (q - 1) + s
+//    gradient:  + 3 (qb - 2) + 2 + 3 s    (block Horner, final step, squarings)
+#pragma once
+
+#include <math.h>
+
+namespace qoc {
+
+struct SlicePlan {
+  int s, q, qb;
+};
+
+#if defined(__HIPCC__)
+#define QOC_HD __host__ __device__
+#else
+#define QOC_HD
+#endif
+
+QOC_HD inline int taylor_degree(double r, double ur) {
+  int q = 1;
+  double t = r * r * 0.5;  // r^(q+1)/(q+1)!
+  while (q < 30 && t / (1.0 - r / (q + 2)) > ur) {
+    ++q;
+    t *= r / (q + 1);
+  }
+  return q;
+}
+
+QOC_HD inline int frechet_degree(double r, double ur) {
+  int qb = 2;
+  double t = r * r * 0.5;  // r^qb/qb!
+  while (qb < 31 && t / (1.0 - r / (qb + 1)) > ur) {
+    ++qb;
+    t *= r / qb;
+  }
+  return qb;
+}
+
+QOC_HD inline int plan_cost(int s, int q, int qb, bool grad) {
+  int cost = q - 1 + s;
+  if (grad) cost += 3 * (qb - 2) + 2 + 3 * s;
+  return cost;
+}
+
+QOC_HD inline SlicePlan choose_plan(double theta, double ur, bool grad) {
+  int s0 = 0;
+  while (ldexp(theta, -s0) > 1.0 && s0 < 60) ++s0;
+  SlicePlan best = {s0, 1, 2};
+  int best_cost = 1 << 30;
+  for (int s = s0; s <= s0 + 6; ++s) {
+    double r = ldexp(theta, -s);
+    int q = taylor_degree(r, ur);
+    int qb = frechet_degree(r, ur);
+    int c = plan_cost(s, q, qb, grad);
+    if (c < best_cost) {
+      best_cost = c;
+      best.s = s;
+      best.q = q;
+      best.qb = qb;
+    }
+  }
+  return best;
+}
+
+QOC_HD inline int pack_plan(SlicePlan p) { return p.s | (p.q << 8) | (p.qb << 16); }
+
+}  // namespace qoc

@@ -1,0 +1,283 @@
+"""ctypes binding of libqoc (include/qoc.h).
+
+Argument marshalling only: every step of the GRAPE path runs in the HIP
+kernels of libqoc.so.  PyTorch provides device memory and streams for the
+device entry points.  There is no fallback: if the library is not built, or
+it reports an error, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqoc.so")
+
+QOC_OK = 0
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+_ERRORS = {
+    -1: "QOC_ERR_ARG",
+    -2: "QOC_ERR_NOT_HERMITIAN",
+    -3: "QOC_ERR_NONFINITE",
+    -4: "QOC_ERR_OOM",
+    -5: "QOC_ERR_DEVICE",
+    -6: "QOC_ERR_UNSUPPORTED",
+}
+
+# Every symbol include/qoc.h declares.
+EXPORTS = (
+    "qoc_default_options",
+    "qoc_propagate",
+    "qoc_fidelity",
+    "qoc_gradient",
+    "qoc_workspace_size",
+    "qoc_propagate_dev",
+    "qoc_fidelity_dev",
+    "qoc_gradient_dev",
+    "qoc_slice_plan",
+    "qoc_last_error",
+    "qoc_version",
+)
+
+
+class QocError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("validate", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_uint64),
+        ("reunitarise_tol", ctypes.c_double),
+        ("stream", ctypes.c_void_p),
+        ("chunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqoc.so (after torch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2208_12187_amd/build.py")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime torch was built with)
+    except ImportError:
+        pass
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    opt = ctypes.POINTER(Options)
+    L.qoc_default_options.argtypes = [opt]
+    L.qoc_default_options.restype = None
+    L.qoc_propagate.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, opt]
+    L.qoc_fidelity.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, opt]
+    L.qoc_gradient.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, opt]
+    L.qoc_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.qoc_workspace_size.restype = sz
+    L.qoc_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, sz, opt]
+    L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
+    L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
+    L.qoc_slice_plan.argtypes = [i32, i32, i32, vp, vp, vp, dbl, i32, i32, vp]
+    L.qoc_last_error.restype = ctypes.c_char_p
+    L.qoc_version.restype = ctypes.c_char_p
+    for name in ("qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
+                 "qoc_gradient_dev", "qoc_slice_plan"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != QOC_OK:
+        raise QocError(rc, lib().qoc_last_error().decode())
+
+
+def options(precision="fp64", validate=False, chunk=0, stream=None) -> Options:
+    o = Options()
+    lib().qoc_default_options(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.validate = 1 if validate else 0
+    o.chunk = int(chunk)
+    o.stream = stream
+    return o
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ------------------------------------------------------------ host entry points
+
+def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0) -> np.ndarray:
+    """X_N = U_{N-1} ... U_0 (host arrays in, host array out)."""
+    H0, Hc, u = _c128(H0), _c128(Hc), _f64(u)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    out = np.empty((d, d), dtype=np.complex128)
+    o = options(precision, validate, chunk)
+    _check(lib().qoc_propagate(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(out), ctypes.byref(o)))
+    return out
+
+
+def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0) -> float:
+    H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    F = np.zeros(1)
+    o = options(precision, validate, chunk)
+    _check(lib().qoc_fidelity(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), ctypes.byref(o)))
+    return float(F[0])
+
+
+def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0):
+    """(F, grad) with grad[j, k] = dF/du[j, k]."""
+    H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    F = np.zeros(1)
+    grad = np.empty((m, N))
+    o = options(precision, validate, chunk)
+    _check(lib().qoc_gradient(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), _ptr(grad),
+                              ctypes.byref(o)))
+    return float(F[0]), grad
+
+
+def slice_plan(H0, Hc, u, dt, precision="fp64", with_gradient=True) -> np.ndarray:
+    """(N, 3) array of (s, q, qb) per slice, as the kernels choose them."""
+    H0, Hc, u = _c128(H0), _c128(Hc), _f64(u)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    out = np.empty((N, 3), dtype=np.int32)
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(lib().qoc_slice_plan(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), p, 1 if with_gradient else 0,
+                                _ptr(out)))
+    return out
+
+
+def workspace_size(B, d, m, N, precision="fp64", chunk=0) -> int:
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = lib().qoc_workspace_size(B, d, m, N, p, chunk)
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+# ------------------------------------------------------------ device entry points
+
+class Batch:
+    """B problems with shared (d, m, N, dt) resident on a torch device.
+
+    H0 [B, d, d], Hc [B, m, d, d], V [B, d, d] complex128; u [B, m, N] float64.
+    """
+
+    def __init__(self, H0, Hc, u, dt, V=None):
+        import torch
+
+        self.H0 = H0.contiguous()
+        self.Hc = Hc.contiguous()
+        self.u = u.contiguous()
+        self.V = None if V is None else V.contiguous()
+        self.dt = float(dt)
+        assert self.H0.dtype == torch.complex128 and self.Hc.dtype == torch.complex128
+        assert self.u.dtype == torch.float64
+        self.B, self.d = self.H0.shape[0], self.H0.shape[1]
+        self.m, self.N = self.u.shape[1], self.u.shape[2]
+        assert tuple(self.Hc.shape) == (self.B, self.m, self.d, self.d)
+        assert tuple(self.u.shape) == (self.B, self.m, self.N)
+        if self.V is not None:
+            assert self.V.dtype == torch.complex128 and tuple(self.V.shape) == (self.B, self.d, self.d)
+
+    @staticmethod
+    def from_problems(problems, device="cuda"):
+        import torch
+
+        H0 = torch.from_numpy(np.stack([p.H0 for p in problems])).to(device)
+        Hc = torch.from_numpy(np.stack([p.Hc for p in problems])).to(device)
+        u = torch.from_numpy(np.stack([p.u for p in problems])).to(device)
+        V = torch.from_numpy(np.stack([p.V for p in problems])).to(device)
+        dts = {p.dt for p in problems}
+        assert len(dts) == 1, "a batch shares dt"
+        return Batch(H0, Hc, u, dts.pop(), V)
+
+
+class Runner:
+    """Owns a device workspace for repeated calls on batches of one shape."""
+
+    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda"):
+        import torch
+
+        self.B, self.d, self.m, self.N = B, d, m, N
+        self.precision = precision
+        self.chunk = chunk
+        self.ws_bytes = workspace_size(B, d, m, N, precision, chunk)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.device = device
+
+    def _opt(self, stream):
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream))
+
+    def _shape_ok(self, b: Batch):
+        if (b.B, b.d, b.m, b.N) != (self.B, self.d, self.m, self.N):
+            raise ValueError("batch shape does not match the runner")
+
+    def gradient(self, b: Batch, F=None, grad=None, stream=None):
+        """Enqueue F [B] and grad [B, m, N] (float64 device tensors)."""
+        import torch
+
+        self._shape_ok(b)
+        if F is None:
+            F = torch.empty(b.B, dtype=torch.float64, device=self.ws.device)
+        if grad is None:
+            grad = torch.empty((b.B, b.m, b.N), dtype=torch.float64, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_gradient_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(), b.dt,
+                                      b.V.data_ptr(), F.data_ptr(), grad.data_ptr(), self.ws.data_ptr(),
+                                      self.ws_bytes, ctypes.byref(o)))
+        return F, grad
+
+    def fidelity(self, b: Batch, F=None, stream=None):
+        import torch
+
+        self._shape_ok(b)
+        if F is None:
+            F = torch.empty(b.B, dtype=torch.float64, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_fidelity_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(), b.dt,
+                                      b.V.data_ptr(), F.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                      ctypes.byref(o)))
+        return F
+
+    def propagate(self, b: Batch, out=None, stream=None):
+        import torch
+
+        self._shape_ok(b)
+        if out is None:
+            out = torch.empty((b.B, b.d, b.d), dtype=torch.complex128, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_propagate_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(), b.dt,
+                                       out.data_ptr(), self.ws.data_ptr(), self.ws_bytes, ctypes.byref(o)))
+        return out
+
+
+def version() -> str:
+    return lib().qoc_version().decode()

@@ -1,0 +1,132 @@
+"""GPU parity of the HIP GRAPE path against the FP64 CPU oracle.
+
+Tolerances: FP64 path |F - F_ref| <= 1e-10 F_ref and
+max|grad - ref| <= 1e-10 max|ref|; FP32 path |F - F_ref| <= 1e-5 and
+max|grad - ref| <= 1e-4 max|ref|.  Sizes span several 16-row tiles, several
+scan chunks and a ragged last chunk.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import Problem, heisenberg_drift, haar_unitary, make_config, xy_controls
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-10, 1e-10, True), "fp32": (1e-5, 1e-4, False)}
+
+
+def _check(F, grad, ref, prec):
+    ftol, gtol, rel = TOL[prec]
+    bound = ftol * ref["F"] if rel else ftol
+    assert abs(F - ref["F"]) <= bound, (F, ref["F"], abs(F - ref["F"]))
+    gmax = np.max(np.abs(ref["grad"]))
+    err = np.max(np.abs(grad - ref["grad"]))
+    assert err <= gtol * gmax, (err, gmax, err / gmax)
+
+
+def _heis(nq, N, dt, seed):
+    rng = np.random.default_rng(seed)
+    H0 = heisenberg_drift(rng.uniform(0.5, 1.5, nq - 1), rng.normal(0, 0.2, nq))
+    Hc = xy_controls(nq)
+    u = rng.normal(0, 0.5, (Hc.shape[0], N))
+    return Problem(H0, Hc, u, dt, haar_unitary(2 ** nq, rng))
+
+
+CASES = {
+    "cfg1_d2": lambda: make_config(1),
+    "cfg2_d16_N157": lambda: make_config(2, N=157),
+    "d32_N90": lambda: _heis(5, 90, 0.005, 7),
+    "cfg3_d64_N150": lambda: make_config(3, N=150),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_gradient_matches_oracle(gpu_lib, case, prec):
+    from paper_2208_12187_amd import qoc
+
+    p = CASES[case]()
+    print(f"[parity] {case} {prec} d={p.d} m={p.m} N={p.N}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec)
+    _check(F, grad, ref, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_propagate_and_fidelity_match_oracle(gpu_lib, prec):
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(2, N=211)
+    print(f"[parity] propagate/fidelity {prec}", flush=True)
+    ref = oracle.fidelity_ref(p)
+    XN = qoc.propagate(p.H0, p.Hc, p.u, p.dt, prec)
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.max(np.abs(XN - ref["XN"])) < tol
+    F = qoc.fidelity(p.H0, p.Hc, p.u, p.dt, p.V, prec)
+    assert abs(F - ref["F"]) <= (1e-10 * ref["F"] if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 7, 0, 1000])
+def test_chunking_does_not_change_the_result(gpu_lib, chunk):
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(2, N=37)
+    print(f"[parity] chunk={chunk}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp64", chunk=chunk)
+    _check(F, grad, ref, "fp64")
+
+
+@pytest.mark.parametrize("d", [3, 5, 20, 48])
+def test_non_power_of_two_dimensions_are_padded_exactly(gpu_lib, d):
+    from paper_2208_12187_amd import qoc
+
+    rng = np.random.default_rng(d)
+    Z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    H0 = (Z + Z.conj().T) / 4
+    Hc = []
+    for _ in range(3):
+        Z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+        Hc.append((Z + Z.conj().T) / 4)
+    p = Problem(H0, np.array(Hc), rng.normal(0, 0.5, (3, 23)), 0.01, haar_unitary(d, rng))
+    print(f"[parity] padded d={d}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp64")
+    _check(F, grad, ref, "fp64")
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_tiny_slice_counts(gpu_lib, N):
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(3, N=N)
+    print(f"[parity] N={N}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp64")
+    _check(F, grad, ref, "fp64")
+
+
+def test_large_theta_uses_squaring(gpu_lib):
+    """Strong controls and long slices force s > 0 in the plan."""
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(2, N=40)
+    q = Problem(p.H0, p.Hc, 8 * p.u, 0.2, p.V)
+    plan = qoc.slice_plan(q.H0, q.Hc, q.u, q.dt, "fp64", True)
+    assert plan[:, 0].max() >= 2
+    print("[parity] squaring", flush=True)
+    ref = oracle.grape_ref(q)
+    for prec in ("fp64", "fp32"):
+        F, grad = qoc.gradient(q.H0, q.Hc, q.u, q.dt, q.V, prec)
+        _check(F, grad, ref, prec)
+
+
+def test_stationary_point_on_gpu(gpu_lib):
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(3, N=60)
+    XN = oracle.fidelity_ref(p)["XN"]
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, XN, "fp64")
+    assert abs(F - 1) < 1e-12
+    assert np.max(np.abs(grad)) < 1e-11
