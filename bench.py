@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""GRAPE forward + gradient throughput on one MI355X.
+
+One step = one pass of the whole hot path (plan, slice propagators, forward
+and backward scans, fidelity, adjoint gradient) over a batch of B independent
+6-qubit Ising problems (d = 64, m = 12 controls, N = 2000 slices,
+dt = 0.002, u ~ N(0, 0.5), Haar-random targets; seeded copies 1..B), with
+all inputs resident in HBM.  value = slice-steps per second of the headline
+precision; the plain FP64 path is timed beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GRAPE slice-steps/s (fwd+grad, d=64) vs plain FP64; p50/p99 request latency"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+CFG = 3  # 6-qubit Ising chain, d = 64
+
+
+def slice_flops(plan: np.ndarray, d: int, m: int) -> dict:
+    """Algorithmic real flops per stage for slices with plan rows (s, q, qb).
+
+    A complex d x d product is 8 d^3 flops.  expm: q - 1 + s products and the
+    assembly (4 m d^2); scans: one product per slice in each direction;
+    adjoint: three products per block Horner step or squaring,
+    3 (qb - 1 + s), plus assembly and the m inner products (12 m d^2)."""
+    s, q, qb = plan[:, 0].astype(np.float64), plan[:, 1].astype(np.float64), plan[:, 2].astype(np.float64)
+    G = 8.0 * d ** 3
+    expm = G * (q - 1 + s) + 4.0 * m * d * d
+    scan = np.full_like(s, 2 * G)
+    adj = G * 3 * (qb - 1 + s) + 12.0 * m * d * d
+    return {"expm": float(expm.sum()), "scan": float(scan.sum()), "adjoint": float(adj.sum())}
+
+
+def time_runner(qoc, torch, runner, batch, steps, warmup):
+    F = torch.empty(batch.B, dtype=torch.float64, device="cuda")
+    grad = torch.empty((batch.B, batch.m, batch.N), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        runner.gradient(batch, F, grad)
+    torch.cuda.synchronize()
+    qoc.stage_times()
+    qoc.stage_timing(True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        runner.gradient(batch, F, grad)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    qoc.stage_timing(False)
+    stages = qoc.stage_times()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": ms, "wall_s": wall, "stages": stages, "F": F.cpu().numpy(), "grad": grad}
+
+
+def cpu_baseline():
+    """The CPU oracle on one full configuration-3 problem (N = 2000 slices)."""
+    import oracle
+    from workloads import make_config
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    p = make_config(CFG, copy=1)
+    t0 = time.perf_counter()
+    oracle.grape_ref(p)
+    dt = time.perf_counter() - t0
+    return {"value": p.N / dt, "unit": "slice-steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one configuration-3 problem (d=64, m=12, N={p.N}) fwd+grad, {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_12187_amd import qoc
+    from workloads import make_batch
+
+    torch.cuda.init()
+    B = args.batch
+    problems = make_batch(CFG, B)
+    d, m, N = problems[0].d, problems[0].m, problems[0].N
+    batch = qoc.Batch.from_problems(problems)
+    plans = {pr: np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, pr, True) for p in problems])
+             for pr in ("fp32", "fp64")}
+    flops = {pr: slice_flops(plans[pr], d, m) for pr in plans}
+
+    def leg(prec, steps, bsz=B, bat=batch):
+        r = qoc.Runner(bsz, d, m, N, prec)
+        out = time_runner(qoc, torch, r, bat, steps, args.warmup)
+        del r
+        torch.cuda.empty_cache()
+        return out
+
+    head = leg(args.precision, args.steps)
+    ms = head["ms_per_step"]
+    value = B * N / (ms / 1e3)
+
+    # roofline of the dominant kernel (adjoint), from its own event timings
+    adj_ms, adj_n = head["stages"]["adjoint"]
+    adj_avg_s = adj_ms / max(adj_n, 1) / 1e3
+    adj_flops = flops[args.precision]["adjoint"]
+    achieved = adj_flops / adj_avg_s / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "k_adjoint",
+                "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4)}
+    total_flops = sum(flops[args.precision].values())
+    stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in head["stages"].items() if v[1]}
+
+    extra = {}
+    if not args.no_fp64 and args.precision != "fp64":
+        f64 = leg("fp64", max(2, args.steps // 4))
+        v64 = B * N / (f64["ms_per_step"] / 1e3)
+        extra["fp64"] = {"value": round(v64, 1), "ms_per_step": round(f64["ms_per_step"], 3),
+                         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in f64["stages"].items() if v[1]},
+                         "path_tflops": round(sum(flops["fp64"].values()) / (f64["ms_per_step"] / 1e3) / 1e12, 2)}
+        extra["speedup_vs_fp64"] = round(value / v64, 3)
+        extra["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(head["F"] - f64["F"])))
+    if not args.no_b1:
+        b1 = qoc.Batch(batch.H0[:1], batch.Hc[:1], batch.u[:1], batch.dt, batch.V[:1])
+        one = leg(args.precision, args.steps, 1, b1)
+        extra["batch1"] = {"value": round(N / (one["ms_per_step"] / 1e3), 1),
+                           "ms_per_step": round(one["ms_per_step"], 3)}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "slice-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"6-qubit Ising chain GRAPE fwd+grad, d={d}, m={m}, N={N}, dt=0.002, "
+                               f"batch of {B} seeded problems",
+                   "d": d, "m": m, "N": N, "batch": B, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": None if cpu is None else {k: (round(v, 2) if isinstance(v, float) else v)
+                                                  for k, v in cpu.items() if k != "seconds"},
+        "path_tflops": round(total_flops / (ms / 1e3) / 1e12, 2),
+        "stages_ms": stages,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

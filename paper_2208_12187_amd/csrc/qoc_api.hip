@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -259,9 +260,96 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
   return QOC_OK;
 }
 
+// ---------------------------------------------------------------- stage timing
+
+struct StageTimer {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[qoc::ST_COUNT] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+StageTimer& timer() {
+  static StageTimer t;
+  return t;
+}
+
 }  // namespace
 
+namespace qoc {
+void stage_mark(int stage, bool begin, hipStream_t st) {
+  StageTimer& T = timer();
+  if (!T.on) return;
+  std::lock_guard<std::mutex> lk(T.mu);
+  hipEvent_t e = T.get();
+  if (!e) return;
+  if (hipEventRecord(e, st) != hipSuccess) {
+    T.pool.push_back(e);
+    return;
+  }
+  if (begin) {
+    if (T.open[stage]) T.pool.push_back(T.open[stage]);
+    T.open[stage] = e;
+  } else if (T.open[stage]) {
+    T.recs.push_back({stage, T.open[stage], e});
+    T.open[stage] = nullptr;
+  } else {
+    T.pool.push_back(e);
+  }
+}
+}  // namespace qoc
+
 extern "C" {
+
+int qoc_stage_timing(int enable) {
+  timer().on = enable != 0;
+  return QOC_OK;
+}
+
+int qoc_stage_times(int n, double* ms, int64_t* launches) {
+  StageTimer& T = timer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (int i = 0; i < n; ++i) {
+    if (ms) ms[i] = 0;
+    if (launches) launches[i] = 0;
+  }
+  int rc = QOC_OK;
+  for (auto& r : T.recs) {
+    float t = 0;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) rc = fail(QOC_ERR_DEVICE, "stage timing: %s", hipGetErrorString(e));
+    if (r.stage < n) {
+      if (ms) ms[r.stage] += t;
+      if (launches) launches[r.stage] += 1;
+    }
+    T.pool.push_back(r.a);
+    T.pool.push_back(r.b);
+  }
+  T.recs.clear();
+  return rc;
+}
+
+const char* qoc_stage_name(int stage) {
+  static const char* names[] = {"prep", "plan", "expm", "scan", "carry", "mc", "adjoint"};
+  return (stage >= 0 && stage < qoc::ST_COUNT) ? names[stage] : "";
+}
+
 
 void qoc_default_options(qoc_options* opt) {
   if (!opt) return;

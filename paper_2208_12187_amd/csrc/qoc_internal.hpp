@@ -62,6 +62,10 @@ struct Launch {
   hipStream_t stream;
 };
 
+// Stages of the path, for the optional per-stage event timing.
+enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_ADJ, ST_COUNT };
+void stage_mark(int stage, bool begin, hipStream_t st);
+
 // Enqueue the whole hot path for one launch.  Returns a hipError_t.
 hipError_t launch_path(int precision, int D, const Launch& L);
 

@@ -500,19 +500,33 @@ static hipError_t run(const Launch& L, double ur) {
   hipStream_t st = L.stream;
   const bool bwd = (L.flags & RUN_BWD) != 0;
   const bool grad = (L.flags & RUN_GRAD) != 0;
+  stage_mark(ST_PREP, true, st);
   hipLaunchKernelGGL((k_prep<T, D>), dim3(L.nprob, L.max_m + 2), dim3(256), 0, st, L.descs);
+  stage_mark(ST_PREP, false, st);
+  stage_mark(ST_PLAN, true, st);
   hipLaunchKernelGGL(k_plan, dim3((L.total_slices + 255) / 256), dim3(256), 0, st, L.descs, L.nprob, L.uniformN,
                      L.slice_start, L.total_slices, ur, grad ? 1 : 0);
+  stage_mark(ST_PLAN, false, st);
+  stage_mark(ST_EXPM, true, st);
   hipLaunchKernelGGL((k_expm<T, D>), dim3(L.total_slices), dim3(NT), 0, st, L.descs, L.nprob, L.uniformN,
                      L.slice_start, L.total_slices);
+  stage_mark(ST_EXPM, false, st);
+  stage_mark(ST_SCAN, true, st);
   hipLaunchKernelGGL((k_scan_local<T, D>), dim3(L.total_chunks, bwd ? 2 : 1), dim3(NT), 0, st, L.descs, L.nprob,
                      L.uniformP, L.chunk_start, L.total_chunks);
+  stage_mark(ST_SCAN, false, st);
+  stage_mark(ST_CARRY, true, st);
   hipLaunchKernelGGL((k_carry<T, D>), dim3(L.nprob, bwd ? 2 : 1), dim3(NT), 0, st, L.descs);
+  stage_mark(ST_CARRY, false, st);
   if (grad) {
+    stage_mark(ST_MC, true, st);
     hipLaunchKernelGGL((k_mc<T, D>), dim3(L.total_chunks), dim3(NT), 0, st, L.descs, L.nprob, L.uniformP,
                        L.chunk_start, L.total_chunks);
+    stage_mark(ST_MC, false, st);
+    stage_mark(ST_ADJ, true, st);
     hipLaunchKernelGGL((k_adjoint<T, D>), dim3(L.total_slices), dim3(NT), 0, st, L.descs, L.nprob, L.uniformN,
                        L.slice_start, L.total_slices);
+    stage_mark(ST_ADJ, false, st);
   }
   return hipGetLastError();
 }

@@ -40,6 +40,9 @@ EXPORTS = (
     "qoc_fidelity_dev",
     "qoc_gradient_dev",
     "qoc_slice_plan",
+    "qoc_stage_timing",
+    "qoc_stage_times",
+    "qoc_stage_name",
     "qoc_last_error",
     "qoc_version",
 )
@@ -91,9 +94,13 @@ def lib() -> ctypes.CDLL:
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
     L.qoc_slice_plan.argtypes = [i32, i32, i32, vp, vp, vp, dbl, i32, i32, vp]
+    L.qoc_stage_timing.argtypes = [i32]
+    L.qoc_stage_times.argtypes = [i32, vp, vp]
+    L.qoc_stage_name.argtypes = [i32]
+    L.qoc_stage_name.restype = ctypes.c_char_p
     L.qoc_last_error.restype = ctypes.c_char_p
     L.qoc_version.restype = ctypes.c_char_p
-    for name in ("qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
+    for name in ("qoc_stage_timing", "qoc_stage_times", "qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
                  "qoc_gradient_dev", "qoc_slice_plan"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -277,6 +284,23 @@ class Runner:
         _check(lib().qoc_propagate_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(), b.dt,
                                        out.data_ptr(), self.ws.data_ptr(), self.ws_bytes, ctypes.byref(o)))
         return out
+
+
+STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "adjoint")
+
+
+def stage_timing(enable: bool):
+    """Record hipEvents around every kernel stage of subsequent launches."""
+    _check(lib().qoc_stage_timing(1 if enable else 0))
+
+
+def stage_times() -> dict:
+    """{stage: (total_ms, launches)} since the last call; waits for the events."""
+    n = len(STAGES)
+    ms = np.zeros(n)
+    cnt = np.zeros(n, dtype=np.int64)
+    _check(lib().qoc_stage_times(n, _ptr(ms), _ptr(cnt)))
+    return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
 
 def version() -> str:
