@@ -49,6 +49,7 @@ struct Layout {
   size_t desc_bytes;  // descriptor table at the start of the workspace
   size_t Hint, Vint, norms, sq, delta, xprev, bloc, tf, tb, cf, cb, mc, small;
   size_t per_prob;
+  size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
   size_t total;
 };
 
@@ -75,7 +76,9 @@ Layout make_layout(int B, int d, int m, int N, int precision, int chunk) {
   Lo.small = o; o = align_up(o + 128);
   Lo.per_prob = o;
   Lo.desc_bytes = align_up((size_t)B * sizeof(ProbDesc));
-  Lo.total = Lo.desc_bytes + (size_t)B * Lo.per_prob;
+  Lo.scratch = Lo.desc_bytes + (size_t)B * Lo.per_prob;
+  Lo.scratch_bytes = Lo.D == 128 ? (size_t)qoc::kScratchSlots * qoc::kScratchMats * mat : 0;
+  Lo.total = Lo.scratch + Lo.scratch_bytes;
   return Lo;
 }
 
@@ -83,7 +86,6 @@ int check_dims(int B, int d, int m, int N, int precision) {
   if (B < 1) return fail(QOC_ERR_ARG, "batch size B = %d must be >= 1", B);
   if (d < 1 || m < 1 || N < 1) return fail(QOC_ERR_ARG, "need d, m, N >= 1 (got d=%d m=%d N=%d)", d, m, N);
   if (d > 128) return fail(QOC_ERR_UNSUPPORTED, "d = %d exceeds the supported maximum 128", d);
-  if (d > 64) return fail(QOC_ERR_UNSUPPORTED, "d = %d: dimensions above 64 are not built into this library", d);
   if (precision != QOC_FP64 && precision != QOC_FP32)
     return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
   return QOC_OK;
@@ -195,6 +197,7 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   L.max_m = m;
   L.flags = flags;
   L.stream = st;
+  L.scratch = Lo.scratch_bytes ? base + Lo.scratch : nullptr;
   e = qoc::launch_path(opt.precision, Lo.D, L);
   if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
   return QOC_OK;

@@ -119,12 +119,22 @@ __device__ __forceinline__ void panel_zero(Panel<T, D>& P) {
   }
 }
 
+// The constant 1 passed through an empty asm, so that the compiler cannot
+// hoist a whole identity panel out of a loop and keep it live in registers.
+template <typename T>
+__device__ __forceinline__ T opaque_one() {
+  T one = T(1);
+  asm volatile("" : "+v"(one));
+  return one;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void panel_identity(Panel<T, D>& P, const Lane& L) {
+  const T one = opaque_one<T>();
 #pragma unroll
   for (int rb = 0; rb < D / 16; ++rb) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) P.re[rb][r] = (rb == L.w && Prec<T>::rowmap(r, L.g) == L.c16) ? T(1) : T(0);
+    for (int r = 0; r < 4; ++r) P.re[rb][r] = (rb == L.w && Prec<T>::rowmap(r, L.g) == L.c16) ? one : T(0);
     P.im[rb] = 0;
   }
 }

@@ -60,7 +60,13 @@ struct Launch {
   int max_m;
   int flags;
   hipStream_t stream;
+  void* scratch;  // D = 128 only: kScratchSlots per-workgroup regions of kScratchMats matrices
 };
+
+// D = 128 kernels run persistent grids of at most kScratchSlots workgroups;
+// each owns kScratchMats stored matrices of scratch in the workspace.
+constexpr int kScratchSlots = 256;
+constexpr int kScratchMats = 6;
 
 // Stages of the path, for the optional per-stage event timing.
 enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_ADJ, ST_COUNT };

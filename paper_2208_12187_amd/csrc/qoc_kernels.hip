@@ -170,6 +170,120 @@ __device__ __forceinline__ void unpack_sq(int sq, int& s, int& q, int& qb) {
   qb = (sq >> 16) & 255;
 }
 
+// ---------------------------------------------------------------- epilogues
+
+// S = X_N (panel): write X_N if requested, then g = Tr(V^dag X_N) and
+// F = |g|^2 / d^2 with FP64 accumulation.  red: 2 * D/16 doubles of LDS.
+template <typename T, int D>
+__device__ __forceinline__ void fidelity_epilogue(const ProbDesc& P, const Panel<T, D>& S, const Lane& L,
+                                                  double* red) {
+  constexpr int NW = D / 16;
+  const int d = P.d;
+  if (P.XN) {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
+        if (row < d && col < d) {
+          P.XN[2 * (row * d + col)] = (double)S.re[rb][r];
+          P.XN[2 * (row * d + col) + 1] = (double)S.im[rb][r];
+        }
+      }
+  }
+  if (P.Vz) {
+    double gr = 0, gi = 0;
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
+        if (row < d && col < d) {
+          double vr = P.Vz[2 * (row * d + col)], vi = P.Vz[2 * (row * d + col) + 1];
+          double xr = (double)S.re[rb][r], xi = (double)S.im[rb][r];
+          gr += vr * xr + vi * xi;  // conj(v) x
+          gi += vr * xi - vi * xr;
+        }
+      }
+    gr = wave_sum(gr);
+    gi = wave_sum(gi);
+    __syncthreads();
+    if (L.lane == 0) { red[2 * L.w] = gr; red[2 * L.w + 1] = gi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0, b = 0;
+      for (int w = 0; w < NW; ++w) { a += red[2 * w]; b += red[2 * w + 1]; }
+      P.g[0] = a;
+      P.g[1] = b;
+      *P.F = (a * a + b * b) / ((double)d * d);
+    }
+  }
+}
+
+// G = S^dag S (panel): diag[0] = |G - I|_F over the d x d block, FP64 accumulation.
+template <typename T, int D>
+__device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel<T, D>& G, const Lane& L,
+                                                  double* red) {
+  constexpr int NW = D / 16;
+  const int d = P.d;
+  double e2 = 0;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
+      if (row < d && col < d) {
+        double xr = (double)G.re[rb][r] - (row == col ? 1.0 : 0.0), xi = (double)G.im[rb][r];
+        e2 += xr * xr + xi * xi;
+      }
+    }
+  e2 = wave_sum(e2);
+  __syncthreads();
+  if (L.lane == 0) red[L.w] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0;
+    for (int w = 0; w < NW; ++w) a += red[w];
+    P.diag[0] = sqrt(a);
+  }
+}
+
+// Z = Z_k (panel): T_j = Tr(Z^dag Hc[j]) with FP64 accumulation and
+// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  red: 2 x 2 * D/16 doubles of LDS.
+template <typename T, int D>
+__device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
+                                                  double* red) {
+  constexpr int NW = D / 16;
+  const T* H = reinterpret_cast<const T*>(P.Hint);
+  const double gr = P.g[0], gi = P.g[1];
+  const double pref = 2.0 * P.dt / ((double)P.d * P.d);
+  for (int j = 0; j < P.m; ++j) {
+    const T* Hr = H + (size_t)(j + 1) * 2 * D * D;
+    const T* Hi = Hr + D * D;
+    double tr = 0, ti = 0;
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
+        double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
+        double hr = (double)Hr[e], hi = (double)Hi[e];
+        tr += zr * hr + zi * hi;  // conj(z) h
+        ti += zr * hi - zi * hr;
+      }
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    double* rj = red + (j & 1) * 2 * NW;
+    if (L.lane == 0) { rj[2 * L.w] = tr; rj[2 * L.w + 1] = ti; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double a = 0, b = 0;
+      for (int w = 0; w < NW; ++w) { a += rj[2 * w]; b += rj[2 * w + 1]; }
+      P.grad[(size_t)j * P.N + k] = pref * (gr * b - gi * a);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- slice propagators
 
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
@@ -284,71 +398,13 @@ __global__ __launch_bounds__(4 * D) void k_carry(const ProbDesc* __restrict__ de
     c = cn;
   }
   if (bwd) return;
-  // S = X_N.
-  const int d = P.d;
-  if (P.XN) {
-#pragma unroll
-    for (int rb = 0; rb < D / 16; ++rb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
-        if (row < d && col < d) {
-          P.XN[2 * (row * d + col)] = (double)S.re[rb][r];
-          P.XN[2 * (row * d + col) + 1] = (double)S.im[rb][r];
-        }
-      }
-  }
-  if (P.Vz) {
-    double gr = 0, gi = 0;
-#pragma unroll
-    for (int rb = 0; rb < D / 16; ++rb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
-        if (row < d && col < d) {
-          double vr = P.Vz[2 * (row * d + col)], vi = P.Vz[2 * (row * d + col) + 1];
-          double xr = (double)S.re[rb][r], xi = (double)S.im[rb][r];
-          gr += vr * xr + vi * xi;   // conj(v) x
-          gi += vr * xi - vi * xr;
-        }
-      }
-    gr = wave_sum(gr);
-    gi = wave_sum(gi);
-    if (L.lane == 0) { red[2 * L.w] = gr; red[2 * L.w + 1] = gi; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0, b = 0;
-      for (int w = 0; w < NW; ++w) { a += red[2 * w]; b += red[2 * w + 1]; }
-      P.g[0] = a;
-      P.g[1] = b;
-      *P.F = (a * a + b * b) / ((double)d * d);
-    }
-  }
-  // Unitarity residual of X_N (FP64 accumulation of |X^dag X - I|^2).
+  fidelity_epilogue<T, D>(P, S, L, red);
+  // Unitarity residual of X_N: S^dag S from the conjugate transpose in LDS.
   __syncthreads();
   panel_to_lds_ct(lds[0], S, L);
   __syncthreads();
   cgemm(acc, lds[0], S, L, true);
-  double e2 = 0;
-#pragma unroll
-  for (int rb = 0; rb < D / 16; ++rb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int row = 16 * rb + Prec<T>::rowmap(r, L.g), col = 16 * L.w + L.c16;
-      if (row < d && col < d) {
-        double xr = (double)acc.re[rb][r] - (row == col ? 1.0 : 0.0), xi = (double)acc.im[rb][r];
-        e2 += xr * xr + xi * xi;
-      }
-    }
-  e2 = wave_sum(e2);
-  __syncthreads();
-  if (L.lane == 0) red[L.w] = e2;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0;
-    for (int w = 0; w < NW; ++w) a += red[w];
-    P.diag[0] = sqrt(a);
-  }
+  residual_epilogue<T, D>(P, acc, L, red);
 }
 
 // mc[c] = cb[c] cf[c]^dag for every chunk, so that W_k = bloc[k] mc[c] xprev[k]^dag.
@@ -462,34 +518,445 @@ __global__ __launch_bounds__(4 * D) void k_adjoint(const ProbDesc* __restrict__ 
   }
 
   // 5. inner products with the controls (FP64), then the gradient
-  const T* H = reinterpret_cast<const T*>(P.Hint);
-  const double gr = P.g[0], gi = P.g[1];
-  const double pref = 2.0 * P.dt / ((double)P.d * P.d);
-  for (int j = 0; j < P.m; ++j) {
-    const T* Hr = H + (size_t)(j + 1) * 2 * D * D;
-    const T* Hi = Hr + D * D;
-    double tr = 0, ti = 0;
+  gradient_epilogue<T, D>(P, k, A2, L, &red[0][0]);
+}
+
+// ================================================================ d = 128
+//
+// A 128 x 128 complex matrix pair does not fit in LDS (one FP32 matrix is
+// 132 KB with padding, one FP64 matrix 260 KB).  At D = 128 the state of every
+// chain therefore lives in global scratch in PF layout (8 wavefronts, one
+// 16-column panel each), each product accumulates one output panel per
+// wavefront in registers, and the left factor is staged cooperatively into
+// LDS, the whole matrix in FP32 and one 64-column half at a time in FP64.
+// The grids are persistent (at most kScratchSlots workgroups), so that each
+// workgroup owns a fixed scratch region.
+
+template <typename T>
+struct K128 {
+  static constexpr int D = 128, NW = 8, RB = 8;
+  static constexpr int HALVES = sizeof(T) == 8 ? 2 : 1;
+  static constexpr int HC = D / HALVES;             // columns staged at once
+  static constexpr int SD = HC + Prec<T>::PAD;      // LDS row stride
+  static constexpr int LDS_ELEMS = 2 * D * SD;
+  static constexpr int ELEMS = 2 * D * D;
+  static constexpr int KBH = HC / 16;               // k blocks per staged part
+  static constexpr int WPH = NW / HALVES;           // panels per staged part
+};
+
+// Row block rb of this wavefront's panel of a PF matrix.
+template <typename T>
+__device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Prec<T>::v4& im, const T* M, int w,
+                                           int rb, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    re = *reinterpret_cast<const f4*>(M + pf_index<T, 128>(w, 0, 4 * rb, lane));
+    im = *reinterpret_cast<const f4*>(M + pf_index<T, 128>(w, 1, 4 * rb, lane));
+  } else {
 #pragma unroll
-    for (int rb = 0; rb < D / 16; ++rb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
-        double zr = (double)A2.re[rb][r], zi = (double)A2.im[rb][r];
-        double hr = (double)Hr[e], hi = (double)Hi[e];
-        tr += zr * hr + zi * hi;  // conj(z) h
-        ti += zr * hi - zi * hr;
-      }
-    tr = wave_sum(tr);
-    ti = wave_sum(ti);
-    double* rj = red[j & 1];
-    if (L.lane == 0) { rj[2 * L.w] = tr; rj[2 * L.w + 1] = ti; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double a = 0, b = 0;
-      for (int w = 0; w < NW; ++w) { a += rj[2 * w]; b += rj[2 * w + 1]; }
-      P.grad[(size_t)j * P.N + k] = pref * (gr * b - gi * a);
+    for (int plane = 0; plane < 2; ++plane) {
+      d2 a = *reinterpret_cast<const d2*>(M + pf_index<T, 128>(w, plane, 4 * rb, lane));
+      d2 b = *reinterpret_cast<const d2*>(M + pf_index<T, 128>(w, plane, 4 * rb + 2, lane));
+      d4 v;
+      v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+      if (plane == 0) re = v; else im = v;
     }
   }
+}
+
+// acc <- acc + a * (this wavefront's panel of the PF matrix M), one row block
+// at a time so that no second panel is held in registers.
+template <typename T>
+__device__ __forceinline__ void panel_axpy_pf(Panel<T, 128>& acc, T a, const T* M, const Lane& L) {
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb) {
+    typename Prec<T>::v4 re, im;
+    pf_rb_load<T>(re, im, M, L.w, rb, L.lane);
+    acc.re[rb] += a * re;
+    acc.im[rb] += a * im;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Stage part h (columns [h HC, (h+1) HC)) of M (CT = false) or of M^dag
+// (CT = true) into LDS; M is a PF matrix.  Layout as for the D <= 64 LDS
+// matrices, restricted to HC columns.
+template <typename T, bool CT>
+__device__ __forceinline__ void stage128(T* lds, const T* M, int h, const Lane& L) {
+  using K = K128<T>;
+  using v4 = typename Prec<T>::v4;
+  T* lim = lds + K::D * K::SD;
+  if constexpr (!CT) {
+    if (L.w / K::WPH != h) return;
+    const int lw = L.w - h * K::WPH;
+#pragma unroll
+    for (int rb = 0; rb < K::RB; ++rb) {
+      v4 re, im;
+      pf_rb_load<T>(re, im, M, L.w, rb, L.lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int off = (16 * rb + Prec<T>::rowmap(r, L.g)) * K::SD + 16 * lw + Prec<T>::perm(L.c16);
+        lds[off] = re[r];
+        lim[off] = im[r];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    // M^dag[16w + c16][16 rb + rowmap(r, g)] = conj(M[16 rb + rowmap(r, g)][16w + c16])
+#pragma unroll
+    for (int rl = 0; rl < K::RB / K::HALVES; ++rl) {
+      const int rb = h * (K::RB / K::HALVES) + rl;
+      v4 re, im;
+      pf_rb_load<T>(re, im, M, L.w, rb, L.lane);
+      int off = (16 * L.w + L.c16) * K::SD + 16 * rl + 4 * L.g;
+      Prec<T>::st4(lds + off, re);
+      Prec<T>::st4(lim + off, -im);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// acc (+)= M B, M (or M^dag when CT) staged through LDS part by part, B this
+// wavefront's panel of a PF matrix.  Starts and ends every part with a
+// workgroup barrier, so M may have been written by any wavefront.
+template <typename T, bool CT>
+__device__ __forceinline__ void gemm128(Panel<T, 128>& acc, T* lds, const T* M, const T* B, const Lane& L,
+                                        bool zero_acc) {
+  using K = K128<T>;
+  using v4 = typename Prec<T>::v4;
+  const T* lim = lds + K::D * K::SD;
+  if (zero_acc) panel_zero(acc);
+  const int base = L.c16 * K::SD + 4 * L.g;
+#pragma unroll
+  for (int h = 0; h < K::HALVES; ++h) {
+    __syncthreads();
+    stage128<T, CT>(lds, M, h, L);
+    __syncthreads();
+    constexpr int STEPS = K::KBH * K::RB;
+    v4 ar[2], ai[2], br[2], bi[2];
+    ar[0] = Prec<T>::ld4(lds + base);
+    ai[0] = Prec<T>::ld4(lim + base);
+    pf_rb_load<T>(br[0], bi[0], B, L.w, h * K::KBH, L.lane);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+      const int kbl = st / K::RB, mb = st % K::RB;
+      const int cur = st & 1, kcur = kbl & 1;
+      if (st + 1 < STEPS) {
+        const int kn = (st + 1) / K::RB, mn = (st + 1) % K::RB;
+        const int off = base + 16 * mn * K::SD + 16 * kn;
+        ar[cur ^ 1] = Prec<T>::ld4(lds + off);
+        ai[cur ^ 1] = Prec<T>::ld4(lim + off);
+        if (mb == 0 && kbl + 1 < K::KBH) pf_rb_load<T>(br[kcur ^ 1], bi[kcur ^ 1], B, L.w, h * K::KBH + kbl + 1, L.lane);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const T b_r = br[kcur][r];
+        const T b_i = bi[kcur][r];
+        acc.re[mb] = Prec<T>::mfma(ar[cur][r], b_r, acc.re[mb]);
+        acc.im[mb] = Prec<T>::mfma(ar[cur][r], b_i, acc.im[mb]);
+        acc.re[mb] = Prec<T>::mfma(-ai[cur][r], b_i, acc.re[mb]);
+        acc.im[mb] = Prec<T>::mfma(ai[cur][r], b_r, acc.im[mb]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+// out = M^dag (both PF), through LDS part by part.
+template <typename T>
+__device__ __forceinline__ void transpose128(T* out, T* lds, const T* M, const Lane& L) {
+  using K = K128<T>;
+  const T* lim = lds + K::D * K::SD;
+  for (int h = 0; h < K::HALVES; ++h) {
+    __syncthreads();
+    stage128<T, true>(lds, M, h, L);
+    __syncthreads();
+    if (L.w / K::WPH == h) {
+      const int lw = L.w - h * K::WPH;
+      Panel<T, 128> P;
+#pragma unroll
+      for (int rb = 0; rb < K::RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int off = (16 * rb + Prec<T>::rowmap(r, L.g)) * K::SD + 16 * lw + Prec<T>::perm(L.c16);
+          P.re[rb][r] = lds[off];
+          P.im[rb][r] = lim[off];
+        }
+      panel_store(out, P, L);
+    }
+  }
+}
+
+// out (PF) <- sgn * (-i) * c * H_k, all 512 threads, coalesced reads of the
+// planar control matrices.
+template <typename T>
+__device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, double c, double sgn) {
+  constexpr int D = 128;
+  const T* H = reinterpret_cast<const T*>(P.Hint);
+  const T f = (T)(sgn * c);
+  for (int e = threadIdx.x; e < D * D; e += 512) {
+    T hr = H[e], hi = H[D * D + e];
+    for (int j = 0; j < P.m; ++j) {
+      const T uj = (T)P.u[(size_t)j * P.N + k];
+      const T* Hj = H + (size_t)(j + 1) * 2 * D * D;
+      hr += uj * Hj[e];
+      hi += uj * Hj[D * D + e];
+    }
+    const int row = e / D, col = e % D;
+    const int w = col >> 4, c16 = col & 15, rb = row >> 4, rr = row & 15;
+    int r, g;
+    if (sizeof(T) == 4) { g = rr >> 2; r = rr & 3; } else { r = rr >> 2; g = rr & 3; }
+    const int lane = 16 * g + c16, reg = 4 * rb + r;
+    out[pf_index<T, D>(w, 0, reg, lane)] = f * hi;
+    out[pf_index<T, D>(w, 1, reg, lane)] = -f * hr;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T* slot_mat(void* scratch, int i) {
+  return reinterpret_cast<T*>(scratch) + ((size_t)blockIdx.x * kScratchMats + i) * K128<T>::ELEMS;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_expm128(const ProbDesc* __restrict__ descs, int nprob, int uniformN,
+                                                 const int* __restrict__ start, int total, void* scratch) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  Lane L;
+  T* SX = slot_mat<T>(scratch, 0);
+  T* SR = slot_mat<T>(scratch, 1);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int p, k;
+    split_item(item, uniformN, start, nprob, p, k);
+    const ProbDesc& P = descs[p];
+    int s, q, qb;
+    unpack_sq(P.sq[k], s, q, qb);
+    __syncthreads();
+    assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0);
+    __syncthreads();
+    Panel<T, 128> acc;
+    panel_load(acc, SX, L);
+    if (q >= 2) {
+      panel_scale(acc, (T)(1.0 / q));
+      panel_add_identity(acc, L, (T)1);
+      panel_store(SR, acc, L);
+      for (int i = q - 1; i >= 2; --i) {
+        gemm128<T, false>(acc, lds, SX, SR, L, true);
+        panel_scale(acc, (T)(1.0 / i));
+        panel_add_identity(acc, L, (T)1);
+        panel_store(SR, acc, L);
+      }
+      gemm128<T, false>(acc, lds, SX, SR, L, true);
+    }
+    for (int j = 0; j < s; ++j) {
+      panel_store(SR, acc, L);
+      gemm128<T, false>(acc, lds, SR, SR, L, true);
+      panel_axpy_pf(acc, (T)2, SR, L);
+    }
+    panel_store(pf_mat<T, 128>(P.delta, k), acc, L);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_scan128(const ProbDesc* __restrict__ descs, int nprob, int uniformP,
+                                                 const int* __restrict__ start, int total, int dirs) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  Lane L;
+  for (int item = blockIdx.x; item < total * dirs; item += gridDim.x) {
+    const int bwd = item % dirs;
+    int p, c;
+    split_item(item / dirs, uniformP, start, nprob, p, c);
+    const ProbDesc& P = descs[p];
+    const int k0 = c * P.L;
+    const int k1 = min(P.N, k0 + P.L);
+    Panel<T, 128> acc;
+    panel_identity(acc, L);
+    if (!bwd) {
+      panel_store(pf_mat<T, 128>(P.xprev, k0), acc, L);
+      for (int k = k0; k < k1; ++k) {
+        T* cur = pf_mat<T, 128>(P.xprev, k);
+        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.delta, k), cur, L, true);
+        panel_axpy_pf(acc, (T)1, cur, L);
+        panel_store(k + 1 < k1 ? pf_mat<T, 128>(P.xprev, k + 1) : pf_mat<T, 128>(P.tf, c), acc, L);
+      }
+    } else {
+      panel_store(pf_mat<T, 128>(P.bloc, k1 - 1), acc, L);
+      for (int k = k1 - 1; k >= k0; --k) {
+        T* cur = pf_mat<T, 128>(P.bloc, k);
+        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.delta, k), cur, L, true);
+        panel_axpy_pf(acc, (T)1, cur, L);
+        panel_store(k > k0 ? pf_mat<T, 128>(P.bloc, k - 1) : pf_mat<T, 128>(P.tb, c), acc, L);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_carry128(const ProbDesc* __restrict__ descs, int nprob, int dirs,
+                                                  void* scratch) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  __shared__ double red[2 * 8];
+  Lane L;
+  for (int item = blockIdx.x; item < nprob * dirs; item += gridDim.x) {
+    const int bwd = item % dirs;
+    const ProbDesc& P = descs[item / dirs];
+    const int nc = P.P;
+    Panel<T, 128> acc;
+    if (!bwd) {
+      panel_identity(acc, L);
+      panel_store(pf_mat<T, 128>(P.cf, 0), acc, L);
+      for (int c = 0; c < nc; ++c) {
+        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cf, c), L, true);
+        if (c + 1 < nc) panel_store(pf_mat<T, 128>(P.cf, c + 1), acc, L);
+      }
+      fidelity_epilogue<T, 128>(P, acc, L, red);
+      T* SXN = slot_mat<T>(scratch, 0);
+      panel_store(SXN, acc, L);
+      gemm128<T, true>(acc, lds, SXN, SXN, L, true);
+      residual_epilogue<T, 128>(P, acc, L, red);
+    } else {
+      panel_load(acc, reinterpret_cast<const T*>(P.Vint), L);
+      panel_store(pf_mat<T, 128>(P.cb, nc - 1), acc, L);
+      for (int c = nc - 1; c >= 1; --c) {
+        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.tb, c), pf_mat<T, 128>(P.cb, c), L, true);
+        panel_store(pf_mat<T, 128>(P.cb, c - 1), acc, L);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_mc128(const ProbDesc* __restrict__ descs, int nprob, int uniformP,
+                                               const int* __restrict__ start, int total, void* scratch) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  Lane L;
+  T* S0 = slot_mat<T>(scratch, 0);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int p, c;
+    split_item(item, uniformP, start, nprob, p, c);
+    const ProbDesc& P = descs[p];
+    transpose128<T>(S0, lds, pf_mat<T, 128>(P.cf, c), L);
+    Panel<T, 128> acc;
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), S0, L, true);
+    panel_store(pf_mat<T, 128>(P.mc, c), acc, L);
+    __syncthreads();
+  }
+}
+
+// Same steps as k_adjoint, with the chain state in scratch (see above).
+template <typename T>
+__global__ __launch_bounds__(512) void k_adjoint128(const ProbDesc* __restrict__ descs, int nprob, int uniformN,
+                                                    const int* __restrict__ start, int total, void* scratch) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  __shared__ double red[2 * 2 * 8];
+  Lane L;
+  T* S0 = slot_mat<T>(scratch, 0);
+  T* S1 = slot_mat<T>(scratch, 1);
+  T* SE = slot_mat<T>(scratch, 2);
+  T* SX = slot_mat<T>(scratch, 3);
+  T* SR1 = slot_mat<T>(scratch, 4);
+  T* SR2 = slot_mat<T>(scratch, 5);
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int p, k;
+    split_item(item, uniformN, start, nprob, p, k);
+    const ProbDesc& P = descs[p];
+    int s, q, qb;
+    unpack_sq(P.sq[k], s, q, qb);
+    const int c = k / P.L;
+    Panel<T, 128> acc;
+    // W = bloc[k] (mc[c] xprev[k]^dag)
+    transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k), L);
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.mc, c), S0, L, true);
+    panel_store(S1, acc, L);
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.bloc, k), S1, L, true);
+    // E = W / 2^s, R2 = E / qb
+    panel_scale(acc, (T)ldexp(1.0, -s));
+    panel_store(SE, acc, L);
+    panel_scale(acc, (T)(1.0 / qb));
+    panel_store(SR2, acc, L);
+    // X = A^dag / 2^s, R1 = I + X / qb
+    __syncthreads();
+    assemble128<T>(SX, P, k, ldexp(P.dt, -s), -1.0);
+    __syncthreads();
+    panel_load(acc, SX, L);
+    panel_scale(acc, (T)(1.0 / qb));
+    panel_add_identity(acc, L, (T)1);
+    panel_store(SR1, acc, L);
+    for (int i = qb - 1; i >= 2; --i) {
+      const T inv = (T)(1.0 / i);
+      gemm128<T, false>(acc, lds, SX, SR2, L, true);
+      gemm128<T, false>(acc, lds, SE, SR1, L, false);
+      panel_scale(acc, inv);
+      panel_store(SR2, acc, L);  // R2 <- (X R2 + E R1) / i  (own panel; R1 still intact)
+      gemm128<T, false>(acc, lds, SX, SR1, L, true);
+      panel_scale(acc, inv);
+      panel_add_identity(acc, L, (T)1);
+      panel_store(SR1, acc, L);
+    }
+    // D1 = X R1 (into S1) when squaring follows; Q = X R2 + E R1 (into S0 and acc)
+    if (s > 0) {
+      gemm128<T, false>(acc, lds, SX, SR1, L, true);
+      panel_store(S1, acc, L);
+    }
+    gemm128<T, false>(acc, lds, SX, SR2, L, true);
+    gemm128<T, false>(acc, lds, SE, SR1, L, false);
+    for (int j = 0; j < s; ++j) {
+      panel_store(S0, acc, L);                        // Q
+      gemm128<T, false>(acc, lds, S1, S0, L, true);   // D1 Q
+      gemm128<T, false>(acc, lds, S0, S1, L, false);  // + Q D1
+      panel_axpy_pf(acc, (T)2, S0, L);                // Q <- 2Q + D1 Q + Q D1
+      if (j + 1 < s) {
+        // Every wavefront's staging of the old Q and D1 ended before the
+        // barrier inside the last product, so own panels may be replaced.
+        panel_store(S0, acc, L);
+        gemm128<T, false>(acc, lds, S1, S1, L, true);
+        panel_axpy_pf(acc, (T)2, S1, L);              // D1 <- 2 D1 + D1^2
+        panel_store(S1, acc, L);
+        panel_load(acc, S0, L);
+      }
+    }
+    gradient_epilogue<T, 128>(P, k, acc, L, red);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+static hipError_t run128(const Launch& L, double ur) {
+  hipStream_t st = L.stream;
+  const bool bwd = (L.flags & RUN_BWD) != 0;
+  const bool grad = (L.flags & RUN_GRAD) != 0;
+  const int dirs = bwd ? 2 : 1;
+  auto grid = [](int items) { return dim3(items < kScratchSlots ? items : kScratchSlots); };
+  stage_mark(ST_PREP, true, st);
+  hipLaunchKernelGGL((k_prep<T, 128>), dim3(L.nprob, L.max_m + 2), dim3(256), 0, st, L.descs);
+  stage_mark(ST_PREP, false, st);
+  stage_mark(ST_PLAN, true, st);
+  hipLaunchKernelGGL(k_plan, dim3((L.total_slices + 255) / 256), dim3(256), 0, st, L.descs, L.nprob, L.uniformN,
+                     L.slice_start, L.total_slices, ur, grad ? 1 : 0);
+  stage_mark(ST_PLAN, false, st);
+  stage_mark(ST_EXPM, true, st);
+  hipLaunchKernelGGL(k_expm128<T>, grid(L.total_slices), dim3(512), 0, st, L.descs, L.nprob, L.uniformN,
+                     L.slice_start, L.total_slices, L.scratch);
+  stage_mark(ST_EXPM, false, st);
+  stage_mark(ST_SCAN, true, st);
+  hipLaunchKernelGGL(k_scan128<T>, dim3(L.total_chunks * dirs), dim3(512), 0, st, L.descs, L.nprob, L.uniformP,
+                     L.chunk_start, L.total_chunks, dirs);
+  stage_mark(ST_SCAN, false, st);
+  stage_mark(ST_CARRY, true, st);
+  hipLaunchKernelGGL(k_carry128<T>, grid(L.nprob * dirs), dim3(512), 0, st, L.descs, L.nprob, dirs, L.scratch);
+  stage_mark(ST_CARRY, false, st);
+  if (grad) {
+    stage_mark(ST_MC, true, st);
+    hipLaunchKernelGGL(k_mc128<T>, grid(L.total_chunks), dim3(512), 0, st, L.descs, L.nprob, L.uniformP,
+                       L.chunk_start, L.total_chunks, L.scratch);
+    stage_mark(ST_MC, false, st);
+    stage_mark(ST_ADJ, true, st);
+    hipLaunchKernelGGL(k_adjoint128<T>, grid(L.total_slices), dim3(512), 0, st, L.descs, L.nprob, L.uniformN,
+                       L.slice_start, L.total_slices, L.scratch);
+    stage_mark(ST_ADJ, false, st);
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- launcher
@@ -538,12 +1005,14 @@ hipError_t launch_path(int precision, int D, const Launch& L) {
       case 16: return run<double, 16>(L, ur64);
       case 32: return run<double, 32>(L, ur64);
       case 64: return run<double, 64>(L, ur64);
+      case 128: return run128<double>(L, ur64);
     }
   } else if (precision == 1) {
     switch (D) {
       case 16: return run<float, 16>(L, ur32);
       case 32: return run<float, 32>(L, ur32);
       case 64: return run<float, 64>(L, ur32);
+      case 128: return run128<float>(L, ur32);
     }
   }
   return hipErrorInvalidValue;
