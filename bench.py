@@ -23,7 +23,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "GRAPE slice-steps/s (fwd+grad, d=64) vs plain FP64; p50/p99 request latency"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 CFG = 3  # 6-qubit Ising chain, d = 64
 
 
@@ -92,7 +92,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
@@ -112,7 +113,7 @@ def main():
     d, m, N = problems[0].d, problems[0].m, problems[0].N
     batch = qoc.Batch.from_problems(problems)
     plans = {pr: np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, pr, True) for p in problems])
-             for pr in ("fp32", "fp64")}
+             for pr in ("fp32", "fp64", "bf16x3")}
     flops = {pr: slice_flops(plans[pr], d, m) for pr in plans}
 
     def leg(prec, steps, bsz=B, bat=batch):
@@ -147,6 +148,18 @@ def main():
                          "path_tflops": round(sum(flops["fp64"].values()) / (f64["ms_per_step"] / 1e3) / 1e12, 2)}
         extra["speedup_vs_fp64"] = round(value / v64, 3)
         extra["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(head["F"] - f64["F"])))
+    if not args.no_bf16 and args.precision != "bf16x3":
+        b3 = leg("bf16x3", args.steps)
+        v3 = B * N / (b3["ms_per_step"] / 1e3)
+        adj3_ms, adj3_n = b3["stages"]["adjoint"]
+        extra["bf16x3"] = {"value": round(v3, 1), "ms_per_step": round(b3["ms_per_step"], 3),
+                           "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in b3["stages"].items() if v[1]},
+                           "adjoint_fp32_equiv_tflops": round(flops["bf16x3"]["adjoint"] / (adj3_ms / max(adj3_n, 1) / 1e3) / 1e12, 2),
+                           "max_abs_dF_vs_fp32": float(np.max(np.abs(b3["F"] - head["F"]))),
+                           "grad_err_vs_fp32": float((b3["grad"] - head["grad"]).abs().max().item()
+                                                     / head["grad"].abs().max().item())}
+        if "fp64" in extra:
+            extra["bf16x3"]["speedup_vs_fp64"] = round(v3 / extra["fp64"]["value"], 3)
     if not args.no_b1:
         b1 = qoc.Batch(batch.H0[:1], batch.Hc[:1], batch.u[:1], batch.dt, batch.V[:1])
         one = leg(args.precision, args.steps, 1, b1)

@@ -55,13 +55,18 @@ typedef enum {
 typedef enum {
   QOC_FP64 = 0,  /* complex128 GEMMs on FP64 MFMA */
   QOC_FP32 = 1,  /* complex64 GEMMs on FP32 MFMA; norms, traces and inner products in FP64 */
-  QOC_BF16X3 = 2 /* reserved: split-BF16 products with FP32 accumulation */
+  QOC_BF16X3 = 2 /* complex products as three split-BF16 MFMA products (hi*hi + hi*lo +
+                    lo*hi) with FP32 accumulation and FP32 storage; FP64 norms, traces
+                    and inner products; 17 <= d <= 64 */
 } qoc_precision;
 
 typedef struct {
   int32_t precision;      /* qoc_precision; default QOC_FP64 */
   int32_t validate;       /* nonzero: host entry points check Hermiticity and finiteness */
-  uint64_t hbm_budget;    /* reserved for checkpointing; 0 = no limit */
+  uint64_t hbm_budget;    /* bytes for stored propagators of a call; 0 = no limit.
+                             When the N + chunk arrays exceed it, slices are
+                             processed in checkpoint segments and recomputed
+                             for the gradient pass (same results, more work). */
   double reunitarise_tol; /* reserved; < 0 disables */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
   int32_t chunk;          /* slices per scan chunk; 0 = ceil(sqrt(N)) */
@@ -91,11 +96,12 @@ int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const do
  * and dt, stored back to back in device memory:
  *   H0 [B][d][d], Hc [B][m][d][d], u [B][m][N], V [B][d][d]  (qoc_z / double),
  *   F [B], grad [B][m][N], U_total [B][d][d].
- * workspace must hold qoc_workspace_size(...) bytes of device memory, 256-byte
+ * workspace must hold qoc_workspace_size(B, d, m, N, opt->precision, opt->chunk,
+ * opt->hbm_budget) bytes of device memory (0 for invalid sizes), 256-byte
  * aligned; its contents need no initialisation and are clobbered.  Calls that
  * share a workspace must be ordered on one stream.
  */
-size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk);
+size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget);
 
 int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                       const void* u, double dt, void* U_total, void* workspace,

@@ -46,6 +46,8 @@ size_t elem_size(int precision) { return precision == QOC_FP64 ? 8 : 4; }
 // Byte offsets of one problem's workspace regions, and the total size.
 struct Layout {
   int D, L, P;
+  int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
+  int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
   size_t Hint, Vint, norms, sq, delta, xprev, bloc, tf, tb, cf, cb, mc, small;
   size_t per_prob;
@@ -53,21 +55,34 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(int B, int d, int m, int N, int precision, int chunk) {
+// hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
+// batch: the three per-slice arrays plus the five per-chunk arrays.  When the
+// full arrays do not fit, slices are processed in segments of G chunks whose
+// per-slice arrays are recomputed for the adjoint pass (sqrt(N)
+// checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
+Layout make_layout(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
   Layout Lo;
   Lo.D = padded_dim(d);
   Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
   if (Lo.L < 1) Lo.L = 1;
   Lo.P = (N + Lo.L - 1) / Lo.L;
   const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
+  Lo.G = Lo.P;
+  const double full = (double)B * (3.0 * N + 5.0 * Lo.P) * (double)mat;
+  if (hbm_budget > 0 && full > (double)hbm_budget) {
+    const double avail = (double)hbm_budget / B - 5.0 * Lo.P * (double)mat;
+    const double per_chunk = 3.0 * Lo.L * (double)mat;
+    Lo.G = avail >= per_chunk ? (int)std::min<double>(Lo.P, floor(avail / per_chunk)) : 1;
+  }
+  Lo.W = Lo.G >= Lo.P ? N : std::min(N, Lo.G * Lo.L);
   size_t o = 0;
   Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
   Lo.Vint = o; o = align_up(o + mat);
   Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
   Lo.sq = o; o = align_up(o + (size_t)N * 4);
-  Lo.delta = o; o = align_up(o + (size_t)N * mat);
-  Lo.xprev = o; o = align_up(o + (size_t)N * mat);
-  Lo.bloc = o; o = align_up(o + (size_t)N * mat);
+  Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.tb = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
@@ -86,8 +101,10 @@ int check_dims(int B, int d, int m, int N, int precision) {
   if (B < 1) return fail(QOC_ERR_ARG, "batch size B = %d must be >= 1", B);
   if (d < 1 || m < 1 || N < 1) return fail(QOC_ERR_ARG, "need d, m, N >= 1 (got d=%d m=%d N=%d)", d, m, N);
   if (d > 128) return fail(QOC_ERR_UNSUPPORTED, "d = %d exceeds the supported maximum 128", d);
-  if (precision != QOC_FP64 && precision != QOC_FP32)
+  if (precision != QOC_FP64 && precision != QOC_FP32 && precision != QOC_BF16X3)
     return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
+  if (precision == QOC_BF16X3 && (padded_dim(d) < 32 || padded_dim(d) > 64))
+    return fail(QOC_ERR_UNSUPPORTED, "split-BF16 products are built for 17 <= d <= 64 (got d = %d)", d);
   return QOC_OK;
 }
 
@@ -126,6 +143,57 @@ qoc_options defaults() {
   return o;
 }
 
+// Stage sequence of the path.  Without checkpointing: prep, plan, expm,
+// scans, carry, then mc and adjoint for the gradient.  With checkpointing the
+// per-slice arrays hold one segment at a time: a first sweep over segments
+// (expm, scans) yields every chunk total, the carry and mc run once, and a
+// second sweep recomputes each segment's propagators and local products
+// before its adjoint pass.  The recomputation is bitwise identical.
+hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int flags) {
+  using namespace qoc;
+  const int D = Lo.D;
+  const Range all = {0, N, 0, Lo.P, 0};
+  hipError_t e = hipSuccess;
+  auto run = [&](int st, const Range& rg) {
+    if (e == hipSuccess) e = launch_stage(precision, D, st, L, rg);
+  };
+  run(ST_PREP, all);
+  run(ST_PLAN, all);
+  const bool grad = (flags & RUN_GRAD) != 0;
+  if (Lo.G >= Lo.P) {
+    run(ST_EXPM, all);
+    run(ST_SCAN, all);
+    run(ST_CARRY, all);
+    if (grad) {
+      run(ST_MC, all);
+      run(ST_ADJ, all);
+    }
+    return e;
+  }
+  auto segment = [&](int c_lo) {
+    const int c_n = std::min(Lo.G, Lo.P - c_lo);
+    const int s_lo = c_lo * Lo.L;
+    const int s_hi = std::min(N, (c_lo + c_n) * Lo.L);
+    return Range{s_lo, s_hi - s_lo, c_lo, c_n, s_lo};
+  };
+  for (int c = 0; c < Lo.P; c += Lo.G) {
+    const Range rg = segment(c);
+    run(ST_EXPM, rg);
+    run(ST_SCAN, rg);
+  }
+  run(ST_CARRY, all);
+  if (grad) {
+    run(ST_MC, all);
+    for (int c = 0; c < Lo.P; c += Lo.G) {
+      const Range rg = segment(c);
+      run(ST_EXPM, rg);
+      run(ST_SCAN, rg);
+      run(ST_ADJ, rg);
+    }
+  }
+  return e;
+}
+
 // Enqueue the path for a uniform batch whose inputs and outputs are in
 // device memory.  flags: qoc::RUN_* bits.
 int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt, const void* V,
@@ -139,7 +207,7 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   if ((flags & qoc::RUN_GRAD) && !grad) return fail(QOC_ERR_ARG, "grad must be non-null");
   if (!ws) return fail(QOC_ERR_ARG, "workspace must be non-null");
   if (((uintptr_t)ws) % kAlign) return fail(QOC_ERR_ARG, "workspace must be 256-byte aligned");
-  const Layout Lo = make_layout(B, d, m, N, opt.precision, opt.chunk);
+  const Layout Lo = make_layout(B, d, m, N, opt.precision, opt.chunk, opt.hbm_budget);
   if (ws_bytes < Lo.total)
     return fail(QOC_ERR_ARG, "workspace holds %zu bytes, %zu needed", ws_bytes, Lo.total);
 
@@ -198,7 +266,9 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   L.flags = flags;
   L.stream = st;
   L.scratch = Lo.scratch_bytes ? base + Lo.scratch : nullptr;
-  e = qoc::launch_path(opt.precision, Lo.D, L);
+  L.dyn = nullptr;
+  L.dyn_grid = 0;
+  e = enqueue(opt.precision, Lo, L, N, flags);
   if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
   return QOC_OK;
 }
@@ -232,7 +302,7 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
     if (rc) return rc;
   }
   const size_t dd = (size_t)d * d;
-  const size_t ws_bytes = make_layout(1, d, m, N, opt.precision, opt.chunk).total;
+  const size_t ws_bytes = make_layout(1, d, m, N, opt.precision, opt.chunk, opt.hbm_budget).total;
   DevBufs bufs;
   void* dH0 = bufs.alloc(dd * 16);
   void* dHc = bufs.alloc(dd * 16 * m);
@@ -381,9 +451,9 @@ int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const do
                   qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
 }
 
-size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk) {
+size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
   if (check_dims(B, d, m, N, precision)) return 0;
-  return make_layout(B, d, m, N, precision, chunk).total;
+  return make_layout(B, d, m, N, precision, chunk, hbm_budget).total;
 }
 
 int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
@@ -408,7 +478,7 @@ int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const 
                    int precision, int with_gradient, int32_t* plan) {
   if (d < 1 || m < 1 || N < 1 || !H0 || !Hc || !u || !plan || !(dt > 0))
     return fail(QOC_ERR_ARG, "invalid arguments to qoc_slice_plan");
-  if (precision != QOC_FP64 && precision != QOC_FP32)
+  if (precision != QOC_FP64 && precision != QOC_FP32 && precision != QOC_BF16X3)
     return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
   const double ur = precision == QOC_FP64 ? 0x1p-53 : 0x1p-24;
   auto norm1 = [d](const qoc_z* H) {

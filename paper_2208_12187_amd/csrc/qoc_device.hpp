@@ -333,3 +333,38 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 }  // namespace qoc
+
+namespace qoc {
+
+// LDS policy of the FP64 / FP32 products: planar matrices of T as above.
+// Kernels that stage left factors in LDS go through one of these policies,
+// so that the split-BF16 products can use their own LDS format.
+template <typename T, int D>
+struct StdOps {
+  using Tp = T;
+  static constexpr int BYTES = Mat<T, D>::LDS_ELEMS * (int)sizeof(T);
+  __device__ static __forceinline__ void put(void* lds, int row, int col, T re, T im) {
+    T* p = static_cast<T*>(lds);
+    const int off = lds_off<T, D>(row, col);
+    p[off] = re;
+    p[D * Mat<T, D>::SD + off] = im;
+  }
+  __device__ static __forceinline__ void store(void* lds, const Panel<T, D>& P, const Lane& L) {
+    panel_to_lds(static_cast<T*>(lds), P, L);
+  }
+  __device__ static __forceinline__ void store_ct(void* lds, const Panel<T, D>& P, const Lane& L) {
+    panel_to_lds_ct(static_cast<T*>(lds), P, L);
+  }
+  __device__ static __forceinline__ void load(Panel<T, D>& P, const void* lds, const Lane& L) {
+    panel_from_lds(P, static_cast<const T*>(lds), L);
+  }
+  __device__ static __forceinline__ void load_ct(Panel<T, D>& P, const void* lds, const Lane& L) {
+    panel_from_lds_ct(P, static_cast<const T*>(lds), L);
+  }
+  __device__ static __forceinline__ void gemm(Panel<T, D>& acc, const void* lds, const Panel<T, D>& P, const Lane& L,
+                                              bool zero_acc) {
+    cgemm(acc, static_cast<const T*>(lds), P, L, zero_acc);
+  }
+};
+
+}  // namespace qoc

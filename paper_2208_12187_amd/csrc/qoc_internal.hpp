@@ -61,6 +61,10 @@ struct Launch {
   int flags;
   hipStream_t stream;
   void* scratch;  // D = 128 only: kScratchSlots per-workgroup regions of kScratchMats matrices
+  // Engine launches: item counts and prefix sums in device memory (see Work)
+  // and a fixed persistent grid size; null / 0 for API launches.
+  const int* dyn;
+  int dyn_grid;
 };
 
 // D = 128 kernels run persistent grids of at most kScratchSlots workgroups;
@@ -72,7 +76,27 @@ constexpr int kScratchMats = 6;
 enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_ADJ, ST_COUNT };
 void stage_mark(int stage, bool begin, hipStream_t st);
 
-// Enqueue the whole hot path for one launch.  Returns a hipError_t.
-hipError_t launch_path(int precision, int D, const Launch& L);
+// Sub-range of a uniform launch: slices [s_lo, s_lo + s_n) and chunks
+// [c_lo, c_lo + c_n) of every problem (s_n / c_n = 0: all, from the start
+// arrays); the per-slice arrays delta / xprev / bloc hold slices from kbase
+// on (checkpointed segments keep only a window of them).
+struct Range {
+  int s_lo, s_n, c_lo, c_n, kbase;
+};
+
+// Work items of one kernel launch.  API launches pass nprob / total / start
+// by value (start = null with a uniform range); engine launches replayed from
+// a captured graph read them from device memory instead:
+// dyn[0] = nprob, dyn[1] = total items, dyn[2 .. 2 + nprob] = item prefix sums.
+struct Work {
+  const ProbDesc* descs;
+  int nprob, total;
+  const int* start;
+  Range rg;
+  const int* dyn;
+};
+
+// Enqueue one stage of the path.  Returns a hipError_t.
+hipError_t launch_stage(int precision, int D, int stage, const Launch& L, const Range& rg);
 
 }  // namespace qoc

@@ -22,6 +22,7 @@
 #include "qoc_device.hpp"
 #include "qoc_internal.hpp"
 #include "qoc_plan.hpp"
+#include "qoc_bf16.hpp"
 
 namespace qoc {
 
@@ -36,16 +37,35 @@ __device__ __forceinline__ int locate(const int* start, int n, int item) {
   return lo;
 }
 
-// Map a flat work item to (problem, local index).
-__device__ __forceinline__ void split_item(int item, int uniform, const int* start, int n, int& p, int& k) {
-  if (uniform > 0) {
-    p = item / uniform;
-    k = item - p * uniform;
+// Map a flat work item to (problem, slice or chunk index).  Uniform launches
+// (count > 0) cover indices [lo, lo + count) of every problem; otherwise the
+// items of problem p are [start[p], start[p + 1]).
+__device__ __forceinline__ void split_item(int item, int lo, int count, const int* start, int n, int& p, int& k) {
+  if (count > 0) {
+    p = item / count;
+    k = lo + (item - p * count);
   } else {
     p = locate(start, n, item);
     k = item - start[p];
   }
 }
+
+// The item counts of a launch (see Work).
+struct Items {
+  int nprob, total;
+  const int* start;
+  __device__ __forceinline__ explicit Items(const Work& W) {
+    if (W.dyn) {
+      nprob = W.dyn[0];
+      total = W.dyn[1];
+      start = W.dyn + 2;
+    } else {
+      nprob = W.nprob;
+      total = W.total;
+      start = W.start;
+    }
+  }
+};
 
 template <typename T, int D>
 __device__ __forceinline__ T* pf_mat(void* base, int i) {
@@ -58,12 +78,8 @@ __device__ __forceinline__ T* pf_mat(void* base, int i) {
 // Hc[j] to planar D x D (zero padded), V to PF; also the FP64 one-norms
 // (largest column sum of moduli) of H0 and Hc[j].
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_prep(const ProbDesc* __restrict__ descs) {
-  const ProbDesc& P = descs[blockIdx.x];
-  const int mat = blockIdx.y;
+__device__ __forceinline__ void prep_one(const ProbDesc& P, int mat, double* colmax) {
   const int d = P.d, m = P.m;
-  if (mat > m + 1) return;
-  __shared__ double colmax[256];
   if (mat <= m) {
     const double* src = mat == 0 ? P.H0z : P.Hcz + (size_t)(mat - 1) * 2 * d * d;
     T* dst = reinterpret_cast<T*>(P.Hint) + (size_t)mat * 2 * D * D;
@@ -90,8 +106,8 @@ __global__ __launch_bounds__(256) void k_prep(const ProbDesc* __restrict__ descs
       __syncthreads();
     }
     if (threadIdx.x == 0) P.norms[mat] = colmax[0];
-  } else {
-    if (P.Vz == nullptr || P.Vint == nullptr) return;
+    __syncthreads();
+  } else if (P.Vz != nullptr && P.Vint != nullptr) {
     T* dst = reinterpret_cast<T*>(P.Vint);
     for (int e = threadIdx.x; e < D * D; e += 256) {
       int row = e / D, col = e % D;
@@ -110,29 +126,44 @@ __global__ __launch_bounds__(256) void k_prep(const ProbDesc* __restrict__ descs
   }
 }
 
+// Convert the caller's complex128 matrices to the compute precision: H0 and
+// Hc[j] to planar D x D (zero padded), V to PF; also the FP64 one-norms
+// (largest column sum of moduli) of H0 and Hc[j].  Items: (problem, matrix
+// index 0..m+1) with index m+1 standing for V; 256 threads per item.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_prep(Work W) {
+  __shared__ double colmax[256];
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
+    int p, mat;
+    split_item(item, 0, W.rg.s_n, I.start, I.nprob, p, mat);
+    prep_one<T, D>(W.descs[p], mat, colmax);
+  }
+}
+
 // ---------------------------------------------------------------- plan
 
 // Per slice: theta = dt (|H0|_1 + sum_j |u[j][k]| |Hc[j]|_1) in FP64, then the
 // scaling exponent and Taylor degrees of choose_plan().
-__global__ __launch_bounds__(256) void k_plan(const ProbDesc* __restrict__ descs, int nprob, int uniformN,
-                                              const int* __restrict__ start, int total, double ur, int grad) {
-  int item = blockIdx.x * 256 + threadIdx.x;
-  if (item >= total) return;
-  int p, k;
-  split_item(item, uniformN, start, nprob, p, k);
-  const ProbDesc& P = descs[p];
-  double th = P.norms[0];
-  for (int j = 0; j < P.m; ++j) th = fma(fabs(P.u[(size_t)j * P.N + k]), P.norms[j + 1], th);
-  th *= P.dt;
-  P.sq[k] = pack_plan(choose_plan(th, ur, grad != 0));
+__global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
+  const Items I(W);
+  for (int item = blockIdx.x * 256 + threadIdx.x; item < I.total; item += gridDim.x * 256) {
+    int p, k;
+    split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
+    const ProbDesc& P = W.descs[p];
+    double th = P.norms[0];
+    for (int j = 0; j < P.m; ++j) th = fma(fabs(P.u[(size_t)j * P.N + k]), P.norms[j + 1], th);
+    th *= P.dt;
+    P.sq[k] = pack_plan(choose_plan(th, ur, grad != 0));
+  }
 }
 
 // ---------------------------------------------------------------- assembly
 
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
-template <typename T, int D>
-__device__ __forceinline__ void assemble(T* lds, const ProbDesc& P, int k, double c, double sgn) {
+template <typename T, int D, typename Ops>
+__device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn) {
   constexpr int NT = Mat<T, D>::NT;
   constexpr int EPT = D * D / NT;
   const T* H = reinterpret_cast<const T*>(P.Hint);
@@ -154,13 +185,10 @@ __device__ __forceinline__ void assemble(T* lds, const ProbDesc& P, int k, doubl
     }
   }
   const T f = (T)(sgn * c);
-  T* im = lds + D * Mat<T, D>::SD;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     int e = threadIdx.x + i * NT;
-    int off = lds_off<T, D>(e / D, e % D);
-    lds[off] = f * hi[i];   // -i f (hr + i hi) = f hi - i f hr
-    im[off] = -f * hr[i];
+    Ops::put(lds, e / D, e % D, f * hi[i], -f * hr[i]);  // -i f (hr + i hi) = f hi - i f hr
   }
 }
 
@@ -289,42 +317,44 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
 // Horner in delta form: R_q = I + X/q, R_i = I + X R_{i+1} / i, Delta = X R_2
 // (X = A_k / 2^s), then s squarings Delta <- 2 Delta + Delta^2.
-template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_expm(const ProbDesc* __restrict__ descs, int nprob,
-                                                         int uniformN, const int* __restrict__ start, int total) {
-  const int item = blockIdx.x;
-  if (item >= total) return;
+template <typename T, int D, typename Ops, bool PERSIST>
+__global__ __launch_bounds__(4 * D) void k_expm(Work W) {
+  __shared__ __align__(16) unsigned char lds[Ops::BYTES];
+  Lane L;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, k;
-  split_item(item, uniformN, start, nprob, p, k);
-  const ProbDesc& P = descs[p];
+  split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
+  const ProbDesc& P = W.descs[p];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
-  __shared__ T lds[Mat<T, D>::LDS_ELEMS];
-  Lane L;
-  assemble<T, D>(lds, P, k, ldexp(P.dt, -s), 1.0);
+  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0);
   __syncthreads();
   Panel<T, D> R, acc;
-  panel_from_lds(R, lds, L);
+  Ops::load(R, lds, L);
   if (q >= 2) {
     panel_scale(R, (T)(1.0 / q));
     panel_add_identity(R, L, (T)1);
     for (int i = q - 1; i >= 2; --i) {
-      cgemm(acc, lds, R, L, true);
+      Ops::gemm(acc, lds, R, L, true);
       R = acc;
       panel_scale(R, (T)(1.0 / i));
       panel_add_identity(R, L, (T)1);
     }
-    cgemm(acc, lds, R, L, true);
+    Ops::gemm(acc, lds, R, L, true);
     R = acc;
   }
   for (int j = 0; j < s; ++j) {
     __syncthreads();
-    panel_to_lds(lds, R, L);
+    Ops::store(lds, R, L);
     __syncthreads();
-    cgemm(acc, lds, R, L, true);
+    Ops::gemm(acc, lds, R, L, true);
     panel_axpby(R, (T)1, acc, (T)2);
   }
-  panel_store(pf_mat<T, D>(P.delta, k), R, L);
+  panel_store(pf_mat<T, D>(P.delta, k - W.rg.kbase), R, L);
+  if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
+  __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- chunked scans
@@ -334,37 +364,38 @@ __global__ __launch_bounds__(4 * D) void k_expm(const ProbDesc* __restrict__ des
 // total.  Backward (blockIdx.y = 1): S = U_k^dag ... U_{k1-1}^dag; stores
 // bloc[k] = S before slice k is applied and the chunk total.  Each step is
 // S <- S + Delta S (or Delta^dag S) with Delta staged in LDS, double-buffered.
-template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_scan_local(const ProbDesc* __restrict__ descs, int nprob,
-                                                               int uniformP, const int* __restrict__ start,
-                                                               int total) {
-  const int item = blockIdx.x;
-  if (item >= total) return;
+template <typename T, int D, typename Ops, bool PERSIST>
+__global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
+  __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
+  Lane L;
   const int bwd = blockIdx.y;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
-  split_item(item, uniformP, start, nprob, p, c);
-  const ProbDesc& P = descs[p];
+  split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+  const ProbDesc& P = W.descs[p];
   const int k0 = c * P.L;
   const int k1 = min(P.N, k0 + P.L);
-  __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
-  Lane L;
   Panel<T, D> S, nxt, acc;
   panel_identity(S, L);
   const int n = k1 - k0;
   int k = bwd ? k1 - 1 : k0;
-  panel_load(nxt, pf_mat<T, D>(P.delta, k), L);
+  panel_load(nxt, pf_mat<T, D>(P.delta, k - W.rg.kbase), L);
   for (int i = 0; i < n; ++i) {
-    T* buf = lds[i & 1];
-    if (bwd) panel_to_lds_ct(buf, nxt, L); else panel_to_lds(buf, nxt, L);
+    void* buf = lds[i & 1];
+    if (bwd) Ops::store_ct(buf, nxt, L); else Ops::store(buf, nxt, L);
     const int kn = bwd ? k - 1 : k + 1;
-    if (i + 1 < n) panel_load(nxt, pf_mat<T, D>(P.delta, kn), L);
-    panel_store(pf_mat<T, D>(bwd ? P.bloc : P.xprev, k), S, L);
+    if (i + 1 < n) panel_load(nxt, pf_mat<T, D>(P.delta, kn - W.rg.kbase), L);
+    panel_store(pf_mat<T, D>(bwd ? P.bloc : P.xprev, k - W.rg.kbase), S, L);
     __syncthreads();
-    cgemm(acc, buf, S, L, true);
+    Ops::gemm(acc, buf, S, L, true);
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
   }
   panel_store(pf_mat<T, D>(bwd ? P.tb : P.tf, c), S, L);
+  if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
+  __syncthreads();
+  }
 }
 
 // One workgroup per (problem, direction): serial product over chunk totals.
@@ -372,13 +403,15 @@ __global__ __launch_bounds__(4 * D) void k_scan_local(const ProbDesc* __restrict
 // accumulation) and the unitarity residual |X_N^dag X_N - I|_F.  Backward:
 // cb[c] = Q_{k1(c)-1}, starting from V.
 template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_carry(const ProbDesc* __restrict__ descs) {
-  const ProbDesc& P = descs[blockIdx.x];
-  const int bwd = blockIdx.y;
+__global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
   __shared__ double red[2 * NW];
   Lane L;
+  const int bwd = blockIdx.y;
+  const Items I(W);
+  for (int p = blockIdx.x; p < I.nprob; p += gridDim.x) {
+  const ProbDesc& P = W.descs[p];
   Panel<T, D> S, nxt, acc;
   const int nc = P.P;
   if (bwd) panel_load(S, reinterpret_cast<const T*>(P.Vint), L); else panel_identity(S, L);
@@ -397,27 +430,29 @@ __global__ __launch_bounds__(4 * D) void k_carry(const ProbDesc* __restrict__ de
     S = acc;
     c = cn;
   }
-  if (bwd) return;
-  fidelity_epilogue<T, D>(P, S, L, red);
-  // Unitarity residual of X_N: S^dag S from the conjugate transpose in LDS.
+  if (!bwd) {
+    fidelity_epilogue<T, D>(P, S, L, red);
+    // Unitarity residual of X_N: S^dag S from the conjugate transpose in LDS.
+    __syncthreads();
+    panel_to_lds_ct(lds[0], S, L);
+    __syncthreads();
+    cgemm(acc, lds[0], S, L, true);
+    residual_epilogue<T, D>(P, acc, L, red);
+  }
   __syncthreads();
-  panel_to_lds_ct(lds[0], S, L);
-  __syncthreads();
-  cgemm(acc, lds[0], S, L, true);
-  residual_epilogue<T, D>(P, acc, L, red);
+  }
 }
 
 // mc[c] = cb[c] cf[c]^dag for every chunk, so that W_k = bloc[k] mc[c] xprev[k]^dag.
 template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_mc(const ProbDesc* __restrict__ descs, int nprob, int uniformP,
-                                                       const int* __restrict__ start, int total) {
-  const int item = blockIdx.x;
-  if (item >= total) return;
-  int p, c;
-  split_item(item, uniformP, start, nprob, p, c);
-  const ProbDesc& P = descs[p];
+__global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
   Lane L;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
+  int p, c;
+  split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+  const ProbDesc& P = W.descs[p];
   Panel<T, D> a, b;
   panel_load(a, pf_mat<T, D>(P.cb, c), L);
   panel_to_lds(lds[0], a, L);
@@ -427,6 +462,8 @@ __global__ __launch_bounds__(4 * D) void k_mc(const ProbDesc* __restrict__ descs
   panel_from_lds_ct(b, lds[1], L);
   cgemm(a, lds[0], b, L, true);
   panel_store(pf_mat<T, D>(P.mc, c), a, L);
+  __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- adjoint / gradient
@@ -440,56 +477,55 @@ __global__ __launch_bounds__(4 * D) void k_mc(const ProbDesc* __restrict__ descs
 //  4. s squarings: [[I + D1, Q], [0, I + D1]]^2 gives D1 <- 2 D1 + D1^2 and
 //     Q <- 2Q + D1 Q + Q D1.  Z_k = Q.
 //  5. T_j = Tr(Z_k^dag Hc[j]) in FP64, grad = (2 dt / d^2) Im(conj(g) T_j).
-template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_adjoint(const ProbDesc* __restrict__ descs, int nprob,
-                                                            int uniformN, const int* __restrict__ start, int total) {
-  const int item = blockIdx.x;
-  if (item >= total) return;
-  int p, k;
-  split_item(item, uniformN, start, nprob, p, k);
-  const ProbDesc& P = descs[p];
+template <typename T, int D, typename Ops, bool PERSIST>
+__global__ __launch_bounds__(4 * D) void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
+  __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
+  __shared__ double red[2][2 * NW];
+  Lane L;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
+  int p, k;
+  split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
+  const ProbDesc& P = W.descs[p];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
   const int c = k / P.L;
-  __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
-  __shared__ double red[2][2 * NW];
-  Lane L;
   Panel<T, D> R1, R2, A1, A2;
 
   // 1. W = bloc[k] (mc[c] xprev[k]^dag)
   panel_load(A1, pf_mat<T, D>(P.mc, c), L);
-  panel_to_lds(lds[0], A1, L);
-  panel_load(A2, pf_mat<T, D>(P.xprev, k), L);
-  panel_to_lds(lds[1], A2, L);
-  panel_load(R2, pf_mat<T, D>(P.bloc, k), L);
+  Ops::store(lds[0], A1, L);
+  panel_load(A2, pf_mat<T, D>(P.xprev, k - W.rg.kbase), L);
+  Ops::store(lds[1], A2, L);
+  panel_load(R2, pf_mat<T, D>(P.bloc, k - W.rg.kbase), L);
   __syncthreads();
-  panel_from_lds_ct(A2, lds[1], L);
-  cgemm(A1, lds[0], A2, L, true);
+  Ops::load_ct(A2, lds[1], L);
+  Ops::gemm(A1, lds[0], A2, L, true);
   __syncthreads();
-  panel_to_lds(lds[0], R2, L);
+  Ops::store(lds[0], R2, L);
   __syncthreads();
-  cgemm(R2, lds[0], A1, L, true);  // R2 = W
+  Ops::gemm(R2, lds[0], A1, L, true);  // R2 = W
   __syncthreads();
 
   // 2. E = W / 2^s, X = A^dag / 2^s
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
-  panel_to_lds(lds[1], R2, L);
-  assemble<T, D>(lds[0], P, k, ldexp(P.dt, -s), -1.0);
+  Ops::store(lds[1], R2, L);
+  assemble<T, D, Ops>(lds[0], P, k, ldexp(P.dt, -s), -1.0);
   __syncthreads();
-  const T* X = lds[0];
-  const T* E = lds[1];
+  const void* X = lds[0];
+  const void* E = lds[1];
 
   // 3. Horner on the block
-  panel_from_lds(R1, X, L);
+  Ops::load(R1, X, L);
   panel_scale(R1, (T)(1.0 / qb));
   panel_add_identity(R1, L, (T)1);
   panel_scale(R2, (T)(1.0 / qb));
   for (int i = qb - 1; i >= 2; --i) {
-    cgemm(A2, X, R2, L, true);
-    cgemm(A2, E, R1, L, false);
-    cgemm(A1, X, R1, L, true);
+    Ops::gemm(A2, X, R2, L, true);
+    Ops::gemm(A2, E, R1, L, false);
+    Ops::gemm(A1, X, R1, L, true);
     const T inv = (T)(1.0 / i);
     R1 = A1;
     panel_scale(R1, inv);
@@ -497,21 +533,21 @@ __global__ __launch_bounds__(4 * D) void k_adjoint(const ProbDesc* __restrict__ 
     R2 = A2;
     panel_scale(R2, inv);
   }
-  cgemm(A2, X, R2, L, true);
-  cgemm(A2, E, R1, L, false);  // A2 = Q (top-right of the delta block)
-  if (s > 0) cgemm(A1, X, R1, L, true);  // A1 = D1 (top-left)
+  Ops::gemm(A2, X, R2, L, true);
+  Ops::gemm(A2, E, R1, L, false);  // A2 = Q (top-right of the delta block)
+  if (s > 0) Ops::gemm(A1, X, R1, L, true);  // A1 = D1 (top-left)
 
   // 4. squarings
   for (int j = 0; j < s; ++j) {
     __syncthreads();
-    panel_to_lds(lds[0], A1, L);
-    panel_to_lds(lds[1], A2, L);
+    Ops::store(lds[0], A1, L);
+    Ops::store(lds[1], A2, L);
     __syncthreads();
-    cgemm(R2, lds[0], A2, L, true);   // D1 Q
-    cgemm(R2, lds[1], A1, L, false);  // + Q D1
+    Ops::gemm(R2, lds[0], A2, L, true);   // D1 Q
+    Ops::gemm(R2, lds[1], A1, L, false);  // + Q D1
     panel_axpby(R2, (T)2, A2, (T)1);  // R2 = 2Q + D1 Q + Q D1
     if (j + 1 < s) {
-      cgemm(R1, lds[0], A1, L, true);
+      Ops::gemm(R1, lds[0], A1, L, true);
       panel_axpby(A1, (T)1, R1, (T)2);
     }
     A2 = R2;
@@ -519,6 +555,9 @@ __global__ __launch_bounds__(4 * D) void k_adjoint(const ProbDesc* __restrict__ 
 
   // 5. inner products with the controls (FP64), then the gradient
   gradient_epilogue<T, D>(P, k, A2, L, &red[0][0]);
+  if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
+  __syncthreads();
+  }
 }
 
 // ================================================================ d = 128
@@ -718,16 +757,16 @@ __device__ __forceinline__ T* slot_mat(void* scratch, int i) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_expm128(const ProbDesc* __restrict__ descs, int nprob, int uniformN,
-                                                 const int* __restrict__ start, int total, void* scratch) {
+__global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   Lane L;
   T* SX = slot_mat<T>(scratch, 0);
   T* SR = slot_mat<T>(scratch, 1);
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
-    split_item(item, uniformN, start, nprob, p, k);
-    const ProbDesc& P = descs[p];
+    split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
+    const ProbDesc& P = W.descs[p];
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     __syncthreads();
@@ -752,39 +791,39 @@ __global__ __launch_bounds__(512) void k_expm128(const ProbDesc* __restrict__ de
       gemm128<T, false>(acc, lds, SR, SR, L, true);
       panel_axpy_pf(acc, (T)2, SR, L);
     }
-    panel_store(pf_mat<T, 128>(P.delta, k), acc, L);
+    panel_store(pf_mat<T, 128>(P.delta, k - W.rg.kbase), acc, L);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_scan128(const ProbDesc* __restrict__ descs, int nprob, int uniformP,
-                                                 const int* __restrict__ start, int total, int dirs) {
+__global__ __launch_bounds__(512) void k_scan128(Work W, int dirs) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   Lane L;
-  for (int item = blockIdx.x; item < total * dirs; item += gridDim.x) {
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total * dirs; item += gridDim.x) {
     const int bwd = item % dirs;
     int p, c;
-    split_item(item / dirs, uniformP, start, nprob, p, c);
-    const ProbDesc& P = descs[p];
+    split_item(item / dirs, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+    const ProbDesc& P = W.descs[p];
     const int k0 = c * P.L;
     const int k1 = min(P.N, k0 + P.L);
     Panel<T, 128> acc;
     panel_identity(acc, L);
     if (!bwd) {
-      panel_store(pf_mat<T, 128>(P.xprev, k0), acc, L);
+      panel_store(pf_mat<T, 128>(P.xprev, k0 - W.rg.kbase), acc, L);
       for (int k = k0; k < k1; ++k) {
-        T* cur = pf_mat<T, 128>(P.xprev, k);
-        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.delta, k), cur, L, true);
+        T* cur = pf_mat<T, 128>(P.xprev, k - W.rg.kbase);
+        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.delta, k - W.rg.kbase), cur, L, true);
         panel_axpy_pf(acc, (T)1, cur, L);
-        panel_store(k + 1 < k1 ? pf_mat<T, 128>(P.xprev, k + 1) : pf_mat<T, 128>(P.tf, c), acc, L);
+        panel_store(k + 1 < k1 ? pf_mat<T, 128>(P.xprev, k + 1 - W.rg.kbase) : pf_mat<T, 128>(P.tf, c), acc, L);
       }
     } else {
-      panel_store(pf_mat<T, 128>(P.bloc, k1 - 1), acc, L);
+      panel_store(pf_mat<T, 128>(P.bloc, k1 - 1 - W.rg.kbase), acc, L);
       for (int k = k1 - 1; k >= k0; --k) {
-        T* cur = pf_mat<T, 128>(P.bloc, k);
-        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.delta, k), cur, L, true);
+        T* cur = pf_mat<T, 128>(P.bloc, k - W.rg.kbase);
+        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.delta, k - W.rg.kbase), cur, L, true);
         panel_axpy_pf(acc, (T)1, cur, L);
-        panel_store(k > k0 ? pf_mat<T, 128>(P.bloc, k - 1) : pf_mat<T, 128>(P.tb, c), acc, L);
+        panel_store(k > k0 ? pf_mat<T, 128>(P.bloc, k - 1 - W.rg.kbase) : pf_mat<T, 128>(P.tb, c), acc, L);
       }
     }
     __syncthreads();
@@ -792,14 +831,14 @@ __global__ __launch_bounds__(512) void k_scan128(const ProbDesc* __restrict__ de
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_carry128(const ProbDesc* __restrict__ descs, int nprob, int dirs,
-                                                  void* scratch) {
+__global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   __shared__ double red[2 * 8];
   Lane L;
-  for (int item = blockIdx.x; item < nprob * dirs; item += gridDim.x) {
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.nprob * dirs; item += gridDim.x) {
     const int bwd = item % dirs;
-    const ProbDesc& P = descs[item / dirs];
+    const ProbDesc& P = W.descs[item / dirs];
     const int nc = P.P;
     Panel<T, 128> acc;
     if (!bwd) {
@@ -827,15 +866,15 @@ __global__ __launch_bounds__(512) void k_carry128(const ProbDesc* __restrict__ d
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_mc128(const ProbDesc* __restrict__ descs, int nprob, int uniformP,
-                                               const int* __restrict__ start, int total, void* scratch) {
+__global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   Lane L;
   T* S0 = slot_mat<T>(scratch, 0);
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, c;
-    split_item(item, uniformP, start, nprob, p, c);
-    const ProbDesc& P = descs[p];
+    split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+    const ProbDesc& P = W.descs[p];
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.cf, c), L);
     Panel<T, 128> acc;
     gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), S0, L, true);
@@ -846,8 +885,7 @@ __global__ __launch_bounds__(512) void k_mc128(const ProbDesc* __restrict__ desc
 
 // Same steps as k_adjoint, with the chain state in scratch (see above).
 template <typename T>
-__global__ __launch_bounds__(512) void k_adjoint128(const ProbDesc* __restrict__ descs, int nprob, int uniformN,
-                                                    const int* __restrict__ start, int total, void* scratch) {
+__global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   __shared__ double red[2 * 2 * 8];
   Lane L;
@@ -857,19 +895,20 @@ __global__ __launch_bounds__(512) void k_adjoint128(const ProbDesc* __restrict__
   T* SX = slot_mat<T>(scratch, 3);
   T* SR1 = slot_mat<T>(scratch, 4);
   T* SR2 = slot_mat<T>(scratch, 5);
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
-    split_item(item, uniformN, start, nprob, p, k);
-    const ProbDesc& P = descs[p];
+    split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
+    const ProbDesc& P = W.descs[p];
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     const int c = k / P.L;
     Panel<T, 128> acc;
     // W = bloc[k] (mc[c] xprev[k]^dag)
-    transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k), L);
+    transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k - W.rg.kbase), L);
     gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.mc, c), S0, L, true);
     panel_store(S1, acc, L);
-    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.bloc, k), S1, L, true);
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S1, L, true);
     // E = W / 2^s, R2 = E / qb
     panel_scale(acc, (T)ldexp(1.0, -s));
     panel_store(SE, acc, L);
@@ -921,101 +960,157 @@ __global__ __launch_bounds__(512) void k_adjoint128(const ProbDesc* __restrict__
   }
 }
 
-template <typename T>
-static hipError_t run128(const Launch& L, double ur) {
-  hipStream_t st = L.stream;
-  const bool bwd = (L.flags & RUN_BWD) != 0;
-  const bool grad = (L.flags & RUN_GRAD) != 0;
-  const int dirs = bwd ? 2 : 1;
-  auto grid = [](int items) { return dim3(items < kScratchSlots ? items : kScratchSlots); };
-  stage_mark(ST_PREP, true, st);
-  hipLaunchKernelGGL((k_prep<T, 128>), dim3(L.nprob, L.max_m + 2), dim3(256), 0, st, L.descs);
-  stage_mark(ST_PREP, false, st);
-  stage_mark(ST_PLAN, true, st);
-  hipLaunchKernelGGL(k_plan, dim3((L.total_slices + 255) / 256), dim3(256), 0, st, L.descs, L.nprob, L.uniformN,
-                     L.slice_start, L.total_slices, ur, grad ? 1 : 0);
-  stage_mark(ST_PLAN, false, st);
-  stage_mark(ST_EXPM, true, st);
-  hipLaunchKernelGGL(k_expm128<T>, grid(L.total_slices), dim3(512), 0, st, L.descs, L.nprob, L.uniformN,
-                     L.slice_start, L.total_slices, L.scratch);
-  stage_mark(ST_EXPM, false, st);
-  stage_mark(ST_SCAN, true, st);
-  hipLaunchKernelGGL(k_scan128<T>, dim3(L.total_chunks * dirs), dim3(512), 0, st, L.descs, L.nprob, L.uniformP,
-                     L.chunk_start, L.total_chunks, dirs);
-  stage_mark(ST_SCAN, false, st);
-  stage_mark(ST_CARRY, true, st);
-  hipLaunchKernelGGL(k_carry128<T>, grid(L.nprob * dirs), dim3(512), 0, st, L.descs, L.nprob, dirs, L.scratch);
-  stage_mark(ST_CARRY, false, st);
-  if (grad) {
-    stage_mark(ST_MC, true, st);
-    hipLaunchKernelGGL(k_mc128<T>, grid(L.total_chunks), dim3(512), 0, st, L.descs, L.nprob, L.uniformP,
-                       L.chunk_start, L.total_chunks, L.scratch);
-    stage_mark(ST_MC, false, st);
-    stage_mark(ST_ADJ, true, st);
-    hipLaunchKernelGGL(k_adjoint128<T>, grid(L.total_slices), dim3(512), 0, st, L.descs, L.nprob, L.uniformN,
-                       L.slice_start, L.total_slices, L.scratch);
-    stage_mark(ST_ADJ, false, st);
-  }
-  return hipGetLastError();
+// ---------------------------------------------------------------- launchers
+
+// Work of an API launch over range rg: uniform counts when rg says so,
+// otherwise the prefix arrays of the launch.
+static inline Work slice_work(const Launch& L, const Range& rg) {
+  return Work{L.descs, L.nprob, rg.s_n > 0 ? L.nprob * rg.s_n : L.total_slices, rg.s_n > 0 ? nullptr : L.slice_start,
+              rg, nullptr};
+}
+static inline Work chunk_work(const Launch& L, const Range& rg) {
+  return Work{L.descs, L.nprob, rg.c_n > 0 ? L.nprob * rg.c_n : L.total_chunks, rg.c_n > 0 ? nullptr : L.chunk_start,
+              rg, nullptr};
+}
+static inline int grid_of(const Launch& L, int items, int cap) {
+  if (L.dyn_grid > 0) return L.dyn_grid;
+  return items < 1 ? 1 : (cap > 0 && items > cap ? cap : items);
 }
 
-// ---------------------------------------------------------------- launcher
-
-template <typename T, int D>
-static hipError_t run(const Launch& L, double ur) {
+template <typename T, int D, typename Ops>
+static void stage_small(int stage, const Launch& L, const Range& rg, double ur) {
   constexpr int NT = Mat<T, D>::NT;
   hipStream_t st = L.stream;
-  const bool bwd = (L.flags & RUN_BWD) != 0;
-  const bool grad = (L.flags & RUN_GRAD) != 0;
-  stage_mark(ST_PREP, true, st);
-  hipLaunchKernelGGL((k_prep<T, D>), dim3(L.nprob, L.max_m + 2), dim3(256), 0, st, L.descs);
-  stage_mark(ST_PREP, false, st);
-  stage_mark(ST_PLAN, true, st);
-  hipLaunchKernelGGL(k_plan, dim3((L.total_slices + 255) / 256), dim3(256), 0, st, L.descs, L.nprob, L.uniformN,
-                     L.slice_start, L.total_slices, ur, grad ? 1 : 0);
-  stage_mark(ST_PLAN, false, st);
-  stage_mark(ST_EXPM, true, st);
-  hipLaunchKernelGGL((k_expm<T, D>), dim3(L.total_slices), dim3(NT), 0, st, L.descs, L.nprob, L.uniformN,
-                     L.slice_start, L.total_slices);
-  stage_mark(ST_EXPM, false, st);
-  stage_mark(ST_SCAN, true, st);
-  hipLaunchKernelGGL((k_scan_local<T, D>), dim3(L.total_chunks, bwd ? 2 : 1), dim3(NT), 0, st, L.descs, L.nprob,
-                     L.uniformP, L.chunk_start, L.total_chunks);
-  stage_mark(ST_SCAN, false, st);
-  stage_mark(ST_CARRY, true, st);
-  hipLaunchKernelGGL((k_carry<T, D>), dim3(L.nprob, bwd ? 2 : 1), dim3(NT), 0, st, L.descs);
-  stage_mark(ST_CARRY, false, st);
-  if (grad) {
-    stage_mark(ST_MC, true, st);
-    hipLaunchKernelGGL((k_mc<T, D>), dim3(L.total_chunks), dim3(NT), 0, st, L.descs, L.nprob, L.uniformP,
-                       L.chunk_start, L.total_chunks);
-    stage_mark(ST_MC, false, st);
-    stage_mark(ST_ADJ, true, st);
-    hipLaunchKernelGGL((k_adjoint<T, D>), dim3(L.total_slices), dim3(NT), 0, st, L.descs, L.nprob, L.uniformN,
-                       L.slice_start, L.total_slices);
-    stage_mark(ST_ADJ, false, st);
+  const int dirs = (L.flags & RUN_BWD) ? 2 : 1;
+  const int grad = (L.flags & RUN_GRAD) ? 1 : 0;
+  const Range all = {0, L.uniformN, 0, L.uniformP, rg.kbase};
+  const Work dyn = L.dyn ? Work{L.descs, 0, 0, nullptr, Range{0, 0, 0, 0, 0}, L.dyn} : Work{};
+  switch (stage) {
+    case ST_PREP: {
+      Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob * (L.max_m + 2), nullptr,
+                                  Range{0, L.max_m + 2, 0, 0, 0}, nullptr};
+      hipLaunchKernelGGL((k_prep<T, D>), dim3(grid_of(L, w.total, 0)), dim3(256), 0, st, w);
+      break;
+    }
+    case ST_PLAN: {
+      Work w = L.dyn ? dyn : slice_work(L, all);
+      hipLaunchKernelGGL(k_plan, dim3(L.dyn ? L.dyn_grid : (w.total + 255) / 256), dim3(256), 0, st, w, ur, grad);
+      break;
+    }
+    case ST_EXPM: {
+      Work w = L.dyn ? dyn : slice_work(L, rg);
+      if (L.dyn) hipLaunchKernelGGL((k_expm<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      else hipLaunchKernelGGL((k_expm<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      break;
+    }
+    case ST_SCAN: {
+      Work w = L.dyn ? dyn : chunk_work(L, rg);
+      if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), dim3(grid_of(L, w.total, 0), dirs), dim3(NT), 0, st, w);
+      else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), dim3(grid_of(L, w.total, 0), dirs), dim3(NT), 0, st, w);
+      break;
+    }
+    case ST_CARRY: {
+      Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob, nullptr, all, nullptr};
+      hipLaunchKernelGGL((k_carry<T, D>), dim3(grid_of(L, L.nprob, 0), dirs), dim3(NT), 0, st, w);
+      break;
+    }
+    case ST_MC: {
+      Work w = L.dyn ? dyn : chunk_work(L, all);
+      hipLaunchKernelGGL((k_mc<T, D>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      break;
+    }
+    case ST_ADJ: {
+      Work w = L.dyn ? dyn : slice_work(L, rg);
+      if (L.dyn) hipLaunchKernelGGL((k_adjoint<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      else hipLaunchKernelGGL((k_adjoint<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      break;
+    }
   }
-  return hipGetLastError();
 }
 
-hipError_t launch_path(int precision, int D, const Launch& L) {
+template <typename T>
+static void stage_128(int stage, const Launch& L, const Range& rg, double ur) {
+  hipStream_t st = L.stream;
+  const int dirs = (L.flags & RUN_BWD) ? 2 : 1;
+  const int grad = (L.flags & RUN_GRAD) ? 1 : 0;
+  const Range all = {0, L.uniformN, 0, L.uniformP, rg.kbase};
+  const Work dyn = L.dyn ? Work{L.descs, 0, 0, nullptr, Range{0, 0, 0, 0, 0}, L.dyn} : Work{};
+  const int cap = kScratchSlots;
+  switch (stage) {
+    case ST_PREP: {
+      Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob * (L.max_m + 2), nullptr,
+                                  Range{0, L.max_m + 2, 0, 0, 0}, nullptr};
+      hipLaunchKernelGGL((k_prep<T, 128>), dim3(grid_of(L, w.total, 0)), dim3(256), 0, st, w);
+      break;
+    }
+    case ST_PLAN: {
+      Work w = L.dyn ? dyn : slice_work(L, all);
+      hipLaunchKernelGGL(k_plan, dim3(L.dyn ? L.dyn_grid : (w.total + 255) / 256), dim3(256), 0, st, w, ur, grad);
+      break;
+    }
+    case ST_EXPM: {
+      Work w = L.dyn ? dyn : slice_work(L, rg);
+      hipLaunchKernelGGL(k_expm128<T>, dim3(grid_of(L, w.total, cap)), dim3(512), 0, st, w, L.scratch);
+      break;
+    }
+    case ST_SCAN: {
+      Work w = L.dyn ? dyn : chunk_work(L, rg);
+      hipLaunchKernelGGL(k_scan128<T>, dim3(grid_of(L, w.total * dirs, 0)), dim3(512), 0, st, w, dirs);
+      break;
+    }
+    case ST_CARRY: {
+      Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob, nullptr, all, nullptr};
+      hipLaunchKernelGGL(k_carry128<T>, dim3(grid_of(L, L.nprob * dirs, cap)), dim3(512), 0, st, w, dirs,
+                         L.scratch);
+      break;
+    }
+    case ST_MC: {
+      Work w = L.dyn ? dyn : chunk_work(L, all);
+      hipLaunchKernelGGL(k_mc128<T>, dim3(grid_of(L, w.total, cap)), dim3(512), 0, st, w, L.scratch);
+      break;
+    }
+    case ST_ADJ: {
+      Work w = L.dyn ? dyn : slice_work(L, rg);
+      hipLaunchKernelGGL(k_adjoint128<T>, dim3(grid_of(L, w.total, cap)), dim3(512), 0, st, w, L.scratch);
+      break;
+    }
+  }
+}
+
+hipError_t launch_stage(int precision, int D, int stage, const Launch& L, const Range& rg) {
   const double ur64 = 0x1p-53, ur32 = 0x1p-24;
+  stage_mark(stage, true, L.stream);
+  bool ok = true;
   if (precision == 0) {
     switch (D) {
-      case 16: return run<double, 16>(L, ur64);
-      case 32: return run<double, 32>(L, ur64);
-      case 64: return run<double, 64>(L, ur64);
-      case 128: return run128<double>(L, ur64);
+      case 16: stage_small<double, 16, StdOps<double, 16>>(stage, L, rg, ur64); break;
+      case 32: stage_small<double, 32, StdOps<double, 32>>(stage, L, rg, ur64); break;
+      case 64: stage_small<double, 64, StdOps<double, 64>>(stage, L, rg, ur64); break;
+      case 128: stage_128<double>(stage, L, rg, ur64); break;
+      default: ok = false;
     }
   } else if (precision == 1) {
     switch (D) {
-      case 16: return run<float, 16>(L, ur32);
-      case 32: return run<float, 32>(L, ur32);
-      case 64: return run<float, 64>(L, ur32);
-      case 128: return run128<float>(L, ur32);
+      case 16: stage_small<float, 16, StdOps<float, 16>>(stage, L, rg, ur32); break;
+      case 32: stage_small<float, 32, StdOps<float, 32>>(stage, L, rg, ur32); break;
+      case 64: stage_small<float, 64, StdOps<float, 64>>(stage, L, rg, ur32); break;
+      case 128: stage_128<float>(stage, L, rg, ur32); break;
+      default: ok = false;
     }
+  } else if (precision == 2) {
+    // split-BF16 products in the bulk kernels (expm, scans, adjoint); the
+    // carry and chunk products stay FP32
+    switch (D) {
+      case 32: stage_small<float, 32, Bf3Ops<32>>(stage, L, rg, ur32); break;
+      case 64: stage_small<float, 64, Bf3Ops<64>>(stage, L, rg, ur32); break;
+      default: ok = false;
+    }
+  } else {
+    ok = false;
   }
-  return hipErrorInvalidValue;
+  stage_mark(stage, false, L.stream);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace qoc

@@ -88,7 +88,7 @@ def lib() -> ctypes.CDLL:
     L.qoc_propagate.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, opt]
     L.qoc_fidelity.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, opt]
     L.qoc_gradient.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, opt]
-    L.qoc_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.qoc_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_uint64]
     L.qoc_workspace_size.restype = sz
     L.qoc_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, sz, opt]
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
@@ -112,13 +112,14 @@ def _check(rc: int):
         raise QocError(rc, lib().qoc_last_error().decode())
 
 
-def options(precision="fp64", validate=False, chunk=0, stream=None) -> Options:
+def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0) -> Options:
     o = Options()
     lib().qoc_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.validate = 1 if validate else 0
     o.chunk = int(chunk)
     o.stream = stream
+    o.hbm_budget = int(hbm_budget)
     return o
 
 
@@ -136,32 +137,32 @@ def _ptr(a: np.ndarray):
 
 # ------------------------------------------------------------ host entry points
 
-def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0) -> np.ndarray:
+def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0, hbm_budget=0) -> np.ndarray:
     """X_N = U_{N-1} ... U_0 (host arrays in, host array out)."""
     H0, Hc, u = _c128(H0), _c128(Hc), _f64(u)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     out = np.empty((d, d), dtype=np.complex128)
-    o = options(precision, validate, chunk)
+    o = options(precision, validate, chunk, None, hbm_budget)
     _check(lib().qoc_propagate(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(out), ctypes.byref(o)))
     return out
 
 
-def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0) -> float:
+def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0) -> float:
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
-    o = options(precision, validate, chunk)
+    o = options(precision, validate, chunk, None, hbm_budget)
     _check(lib().qoc_fidelity(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), ctypes.byref(o)))
     return float(F[0])
 
 
-def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0):
+def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0):
     """(F, grad) with grad[j, k] = dF/du[j, k]."""
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
     grad = np.empty((m, N))
-    o = options(precision, validate, chunk)
+    o = options(precision, validate, chunk, None, hbm_budget)
     _check(lib().qoc_gradient(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), _ptr(grad),
                               ctypes.byref(o)))
     return float(F[0]), grad
@@ -178,9 +179,9 @@ def slice_plan(H0, Hc, u, dt, precision="fp64", with_gradient=True) -> np.ndarra
     return out
 
 
-def workspace_size(B, d, m, N, precision="fp64", chunk=0) -> int:
+def workspace_size(B, d, m, N, precision="fp64", chunk=0, hbm_budget=0) -> int:
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    n = lib().qoc_workspace_size(B, d, m, N, p, chunk)
+    n = lib().qoc_workspace_size(B, d, m, N, p, chunk, int(hbm_budget))
     if n == 0:
         _check(-1)
     return int(n)
@@ -227,13 +228,14 @@ class Batch:
 class Runner:
     """Owns a device workspace for repeated calls on batches of one shape."""
 
-    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda"):
+    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda", hbm_budget=0):
         import torch
 
         self.B, self.d, self.m, self.N = B, d, m, N
         self.precision = precision
         self.chunk = chunk
-        self.ws_bytes = workspace_size(B, d, m, N, precision, chunk)
+        self.hbm_budget = int(hbm_budget)
+        self.ws_bytes = workspace_size(B, d, m, N, precision, chunk, hbm_budget)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.device = device
 
@@ -241,7 +243,7 @@ class Runner:
         import torch
 
         st = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
-        return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream))
+        return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream), self.hbm_budget)
 
     def _shape_ok(self, b: Batch):
         if (b.B, b.d, b.m, b.N) != (self.B, self.d, self.m, self.N):

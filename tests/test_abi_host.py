@@ -56,9 +56,9 @@ def test_argument_errors_before_any_launch():
     assert _err(qoc.gradient, p.H0, p.Hc, u, p.dt, p.V, "fp64", True) == -3
     assert _err(qoc.gradient, p.H0, p.Hc, p.u, p.dt, p.V, 7) == -6      # unknown precision
     L = qoc.lib()
-    assert L.qoc_workspace_size(0, 16, 1, 1, 0, 0) == 0
-    assert L.qoc_workspace_size(1, 16, 0, 1, 0, 0) == 0
-    assert L.qoc_workspace_size(1, 16, 1, 1, 5, 0) == 0
+    assert L.qoc_workspace_size(0, 16, 1, 1, 0, 0, 0) == 0
+    assert L.qoc_workspace_size(1, 16, 0, 1, 0, 0, 0) == 0
+    assert L.qoc_workspace_size(1, 16, 1, 1, 5, 0, 0) == 0
 
 
 def test_workspace_size_scales_with_batch_and_precision():

@@ -1,0 +1,106 @@
+"""GPU tests of checkpointing, the autograd boundary, the optimiser driver
+and the full-size differentiation workload (7-qubit Heisenberg, d = 128,
+N = 1000), against the FP64 oracle and central finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_batch, make_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("cfg,N,prec", [(3, 300, "fp32"), (4, 60, "fp64"), (2, 101, "fp64")])
+def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec):
+    import torch
+    from paper_2208_12187_amd import qoc
+
+    problems = make_batch(cfg, 2, N=N)
+    b = qoc.Batch.from_problems(problems)
+    p = problems[0]
+    full = qoc.Runner(2, p.d, p.m, N, prec)
+    D = 128 if p.d > 64 else 64 if p.d > 32 else 32 if p.d > 16 else 16
+    mat = 2 * D * D * (8 if prec == "fp64" else 4)
+    L = int(np.ceil(np.sqrt(N)))
+    P = -(-N // L)
+    small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=2 * (5 * P + 3 * L + 1) * mat)  # one-chunk segments
+    assert small.ws_bytes < full.ws_bytes
+    print(f"[features] checkpoint cfg{cfg} N={N} {prec}: {full.ws_bytes} -> {small.ws_bytes} bytes", flush=True)
+    F1, g1 = full.gradient(b)
+    F2, g2 = small.gradient(b)
+    torch.cuda.synchronize()
+    assert torch.equal(F1, F2)
+    assert torch.equal(g1, g2)
+    ref = oracle.grape_ref(p)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert np.max(np.abs(g2[0].cpu().numpy() - ref["grad"])) <= tol * np.max(np.abs(ref["grad"]))
+
+
+def test_autograd_function_matches_oracle(gpu_lib):
+    import torch
+    from paper_2208_12187_amd.autograd import GrapeProblem, fidelity
+
+    problems = make_batch(2, 2, N=80)
+    prob = GrapeProblem.from_problems(problems)
+    u = torch.from_numpy(np.stack([p.u for p in problems])).cuda().requires_grad_(True)
+    F = fidelity(u, prob)
+    w = torch.tensor([0.3, -1.7], dtype=torch.float64, device="cuda")
+    (F * w).sum().backward()
+    for b, p in enumerate(problems):
+        ref = oracle.grape_ref(p)
+        assert abs(F[b].item() - ref["F"]) <= 1e-10 * ref["F"]
+        g = u.grad[b].cpu().numpy()
+        assert np.max(np.abs(g - w[b].item() * ref["grad"])) <= 1e-10 * np.max(np.abs(ref["grad"])) * 2
+
+
+def test_lbfgs_raises_fidelity(gpu_lib):
+    import torch
+    from paper_2208_12187_amd.autograd import GrapeProblem
+    from paper_2208_12187_amd.optimize import optimise
+
+    # a reachable target: the propagator of known amplitudes, started from a
+    # perturbation of them
+    p = make_config(2, N=200)
+    p = p.with_target(oracle.fidelity_ref(p)["XN"])
+    rng = np.random.default_rng(12)
+    u_start = p.u + rng.uniform(-1.5, 1.5, (p.m, 1))   # per-control offsets: O(1) rotations
+    prob = GrapeProblem.from_problems([p], precision="fp32")
+    u0 = torch.from_numpy(u_start[None]).cuda()
+    u, hist = optimise(prob, u0, iters=10)
+    Fs = [h["F"][0] for h in hist]
+    print(f"[features] lbfgs F: {Fs[0]:.4f} -> {Fs[-1]:.4f}", flush=True)
+    assert Fs[0] < 0.1
+    assert Fs[-1] > 0.9
+    assert all(b >= a - 1e-6 for a, b in zip(Fs, Fs[1:]))
+
+
+def test_differentiation_workload_full_size(gpu_lib):
+    """d = 128, m = 14, N = 1000, FP64 with checkpointing forced by a 64 MB
+    budget: F and the full gradient against the oracle, and central finite
+    differences (h = 1e-6) of the GPU FP64 fidelity on 32 random entries."""
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(4)
+    budget = 64 << 20
+    print("[features] config 4 full size, oracle ...", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp64", hbm_budget=budget)
+    assert abs(F - ref["F"]) <= 1e-10 * ref["F"]
+    gmax = np.max(np.abs(ref["grad"]))
+    assert np.max(np.abs(grad - ref["grad"])) <= 1e-10 * gmax
+    F32, grad32 = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", hbm_budget=budget)
+    print(f"[features] config 4 fp32 |dF| = {abs(F32 - ref['F']):.2e}, "
+          f"grad err = {np.max(np.abs(grad32 - ref['grad'])) / gmax:.2e}", flush=True)
+    assert abs(F32 - ref["F"]) <= 1e-5
+    assert np.max(np.abs(grad32 - ref["grad"])) <= 1e-4 * gmax
+    rng = np.random.default_rng(4)
+    flat = rng.choice(p.m * p.N, size=32, replace=False)
+    h = 1e-6
+    for f in flat:
+        j, k = divmod(int(f), p.N)
+        up, dn = p.u.copy(), p.u.copy()
+        up[j, k] += h
+        dn[j, k] -= h
+        fd = (qoc.fidelity(p.H0, p.Hc, up, p.dt, p.V, "fp64", hbm_budget=budget)
+              - qoc.fidelity(p.H0, p.Hc, dn, p.dt, p.V, "fp64", hbm_budget=budget)) / (2 * h)
+        assert abs(fd - grad[j, k]) <= 1e-4 * max(abs(grad[j, k]), 0.1 * gmax), (j, k, fd, grad[j, k])

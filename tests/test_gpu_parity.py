@@ -13,7 +13,7 @@ from workloads import Problem, heisenberg_drift, haar_unitary, make_config, xy_c
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-10, 1e-10, True), "fp32": (1e-5, 1e-4, False)}
+TOL = {"fp64": (1e-10, 1e-10, True), "fp32": (1e-5, 1e-4, False), "bf16x3": (1e-5, 1e-4, False)}
 
 
 def _check(F, grad, ref, prec):
@@ -175,3 +175,37 @@ def test_d128_squaring_path(gpu_lib):
     for prec in ("fp64", "fp32"):
         F, grad = qoc.gradient(q.H0, q.Hc, q.u, q.dt, q.V, prec)
         _check(F, grad, ref, prec)
+
+
+@pytest.mark.parametrize("case", ["d32_N90", "cfg3_d64_N150"])
+def test_bf16x3_gradient_matches_oracle(gpu_lib, case):
+    from paper_2208_12187_amd import qoc
+
+    p = CASES[case]()
+    print(f"[parity] {case} bf16x3", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "bf16x3")
+    _check(F, grad, ref, "bf16x3")
+    XN = qoc.propagate(p.H0, p.Hc, p.u, p.dt, "bf16x3")
+    assert np.max(np.abs(XN - ref["XN"])) < 1e-4
+
+
+def test_bf16x3_squaring_and_ragged(gpu_lib):
+    from paper_2208_12187_amd import qoc
+
+    p = _heis(5, 41, 0.005, 3)
+    q = Problem(p.H0, p.Hc, 8 * p.u, 0.2, p.V)
+    assert qoc.slice_plan(q.H0, q.Hc, q.u, q.dt, "bf16x3", True)[:, 0].max() >= 2
+    print("[parity] bf16x3 squaring", flush=True)
+    ref = oracle.grape_ref(q)
+    F, grad = qoc.gradient(q.H0, q.Hc, q.u, q.dt, q.V, "bf16x3", chunk=5)
+    _check(F, grad, ref, "bf16x3")
+
+
+def test_bf16x3_rejects_unsupported_sizes(gpu_lib):
+    from paper_2208_12187_amd import qoc
+
+    p = make_config(2, N=5)
+    with pytest.raises(qoc.QocError) as e:
+        qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "bf16x3")
+    assert e.value.code == -6
