@@ -140,6 +140,41 @@ int qoc_stage_timing(int enable);
 int qoc_stage_times(int n, double* ms, int64_t* launches);
 const char* qoc_stage_name(int stage);
 
+/*
+ * Serving engine: continuous batching of forward + gradient requests of
+ * mixed d and N (one precision per engine).
+ *
+ * Requests are queued by qoc_engine_submit (host inputs are copied into the
+ * engine's pinned staging before it returns) and admitted in FIFO order
+ * while their device footprint (qoc_engine_footprint: inputs, outputs and
+ * the stored propagators of the path, about 3 N D^2 c bytes) fits the
+ * engine's device pool and one of max_active descriptor slots is free.
+ * Admitted requests are grouped by padded dimension D (16, 32, 64, 128); each
+ * group has its own stream and a captured graph of the path's kernels that a
+ * tick replays for every request admitted to the group since its previous
+ * tick.  qoc_engine_step harvests finished ticks, admits queued requests
+ * and starts ticks on idle groups (wait != 0: if nothing has finished,
+ * block until one tick does).  qoc_engine_poll returns up to max finished
+ * request ids with their fidelities; qoc_engine_fetch copies a finished
+ * request's gradient (m*N doubles, may be NULL) and releases its staging.
+ * Submitting more than the staging holds returns QOC_ERR_OOM; a request
+ * larger than the device pool is rejected with QOC_ERR_OOM at submit.
+ * Engine calls are serialised by an internal lock.  Stage timing does not
+ * cover engine launches.
+ */
+typedef struct qoc_engine qoc_engine;
+
+uint64_t qoc_engine_footprint(int precision, int d, int m, int N);
+int qoc_engine_create(int precision, uint64_t pool_bytes, uint64_t host_bytes, int max_active,
+                      qoc_engine** engine);
+int qoc_engine_destroy(qoc_engine* engine);
+int qoc_engine_submit(qoc_engine* engine, int d, int m, int N, const qoc_z* H0, const qoc_z* Hc,
+                      const double* u, double dt, const qoc_z* V, int64_t* id);
+int qoc_engine_step(qoc_engine* engine, int wait);
+int qoc_engine_poll(qoc_engine* engine, int max, int64_t* ids, double* F, int* n);
+int qoc_engine_fetch(qoc_engine* engine, int64_t id, double* grad);
+int qoc_engine_stats(qoc_engine* engine, int64_t* queued, int64_t* active, uint64_t* pool_used);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char* qoc_last_error(void);
 

@@ -15,7 +15,12 @@
 #include "qoc_plan.hpp"
 
 using qoc::Launch;
+using qoc::Layout;
 using qoc::ProbDesc;
+using qoc::align_up;
+using qoc::kAlign;
+using qoc::make_layout;
+using qoc::padded_dim;
 
 namespace {
 
@@ -29,72 +34,6 @@ int fail(int code, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return code;
-}
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-int padded_dim(int d) {
-  if (d <= 16) return 16;
-  if (d <= 32) return 32;
-  if (d <= 64) return 64;
-  return 128;
-}
-
-size_t elem_size(int precision) { return precision == QOC_FP64 ? 8 : 4; }
-
-// Byte offsets of one problem's workspace regions, and the total size.
-struct Layout {
-  int D, L, P;
-  int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
-  int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
-  size_t desc_bytes;  // descriptor table at the start of the workspace
-  size_t Hint, Vint, norms, sq, delta, xprev, bloc, tf, tb, cf, cb, mc, small;
-  size_t per_prob;
-  size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
-  size_t total;
-};
-
-// hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
-// batch: the three per-slice arrays plus the five per-chunk arrays.  When the
-// full arrays do not fit, slices are processed in segments of G chunks whose
-// per-slice arrays are recomputed for the adjoint pass (sqrt(N)
-// checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
-Layout make_layout(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
-  Layout Lo;
-  Lo.D = padded_dim(d);
-  Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
-  if (Lo.L < 1) Lo.L = 1;
-  Lo.P = (N + Lo.L - 1) / Lo.L;
-  const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
-  Lo.G = Lo.P;
-  const double full = (double)B * (3.0 * N + 5.0 * Lo.P) * (double)mat;
-  if (hbm_budget > 0 && full > (double)hbm_budget) {
-    const double avail = (double)hbm_budget / B - 5.0 * Lo.P * (double)mat;
-    const double per_chunk = 3.0 * Lo.L * (double)mat;
-    Lo.G = avail >= per_chunk ? (int)std::min<double>(Lo.P, floor(avail / per_chunk)) : 1;
-  }
-  Lo.W = Lo.G >= Lo.P ? N : std::min(N, Lo.G * Lo.L);
-  size_t o = 0;
-  Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
-  Lo.Vint = o; o = align_up(o + mat);
-  Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
-  Lo.sq = o; o = align_up(o + (size_t)N * 4);
-  Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
-  Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
-  Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
-  Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.tb = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.cb = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.mc = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.small = o; o = align_up(o + 128);
-  Lo.per_prob = o;
-  Lo.desc_bytes = align_up((size_t)B * sizeof(ProbDesc));
-  Lo.scratch = Lo.desc_bytes + (size_t)B * Lo.per_prob;
-  Lo.scratch_bytes = Lo.D == 128 ? (size_t)qoc::kScratchSlots * qoc::kScratchMats * mat : 0;
-  Lo.total = Lo.scratch + Lo.scratch_bytes;
-  return Lo;
 }
 
 int check_dims(int B, int d, int m, int N, int precision) {
@@ -216,38 +155,11 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   const size_t dd = (size_t)d * d;
   for (int b = 0; b < B; ++b) {
     char* pb = base + Lo.desc_bytes + (size_t)b * Lo.per_prob;
-    ProbDesc& P = descs[b];
-    memset(&P, 0, sizeof P);
-    P.d = d;
-    P.D = Lo.D;
-    P.m = m;
-    P.N = N;
-    P.L = Lo.L;
-    P.P = Lo.P;
-    P.flags = flags;
-    P.dt = dt;
-    P.H0z = static_cast<const double*>(H0) + 2 * dd * b;
-    P.Hcz = static_cast<const double*>(Hc) + 2 * dd * m * b;
-    P.u = static_cast<const double*>(u) + (size_t)m * N * b;
-    P.Vz = V ? static_cast<const double*>(V) + 2 * dd * b : nullptr;
-    P.grad = grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr;
-    P.XN = XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr;
-    P.Hint = pb + Lo.Hint;
-    P.Vint = V ? pb + Lo.Vint : nullptr;
-    P.norms = reinterpret_cast<double*>(pb + Lo.norms);
-    P.sq = reinterpret_cast<int*>(pb + Lo.sq);
-    P.delta = pb + Lo.delta;
-    P.xprev = pb + Lo.xprev;
-    P.bloc = pb + Lo.bloc;
-    P.tf = pb + Lo.tf;
-    P.tb = pb + Lo.tb;
-    P.cf = pb + Lo.cf;
-    P.cb = pb + Lo.cb;
-    P.mc = pb + Lo.mc;
-    double* small = reinterpret_cast<double*>(pb + Lo.small);
-    P.g = small;                                           // 2 doubles
-    P.F = F ? static_cast<double*>(F) + b : small + 2;     // 1 double
-    P.diag = small + 4;                                    // 4 doubles
+    fill_desc(descs[b], Lo, pb, d, m, N, dt, flags, static_cast<const double*>(H0) + 2 * dd * b,
+              static_cast<const double*>(Hc) + 2 * dd * m * b, static_cast<const double*>(u) + (size_t)m * N * b,
+              V ? static_cast<const double*>(V) + 2 * dd * b : nullptr, F ? static_cast<double*>(F) + b : nullptr,
+              grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr,
+              XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr);
   }
   hipStream_t st = static_cast<hipStream_t>(opt.stream);
   hipError_t e = hipMemcpyAsync(base, descs.data(), (size_t)B * sizeof(ProbDesc), hipMemcpyHostToDevice, st);
@@ -365,9 +277,13 @@ StageTimer& timer() {
 }  // namespace
 
 namespace qoc {
+void set_last_error(const char* msg) { g_err = msg; }
+
 void stage_mark(int stage, bool begin, hipStream_t st) {
   StageTimer& T = timer();
   if (!T.on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(T.mu);
   hipEvent_t e = T.get();
   if (!e) return;

@@ -4,6 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
 
 namespace qoc {
 
@@ -87,7 +91,8 @@ struct Range {
 // Work items of one kernel launch.  API launches pass nprob / total / start
 // by value (start = null with a uniform range); engine launches replayed from
 // a captured graph read them from device memory instead:
-// dyn[0] = nprob, dyn[1] = total items, dyn[2 .. 2 + nprob] = item prefix sums.
+// dyn[0] = nprob, dyn[1] = total items, dyn[2 .. 2 + nprob] = item prefix
+// sums, dyn[3 + nprob .. 3 + 2 nprob) = index of each problem in descs.
 struct Work {
   const ProbDesc* descs;
   int nprob, total;
@@ -96,7 +101,117 @@ struct Work {
   const int* dyn;
 };
 
+// Message returned by qoc_last_error() on the calling thread.
+void set_last_error(const char* msg);
+
 // Enqueue one stage of the path.  Returns a hipError_t.
 hipError_t launch_stage(int precision, int D, int stage, const Launch& L, const Range& rg);
+
+// ---------------------------------------------------------------- workspace layout
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+inline int padded_dim(int d) {
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  if (d <= 64) return 64;
+  return 128;
+}
+
+inline size_t elem_size(int precision) { return precision == 0 ? 8 : 4; }
+
+// Byte offsets of one problem's workspace regions, and the total size.
+struct Layout {
+  int D, L, P;
+  int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
+  int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
+  size_t desc_bytes;  // descriptor table at the start of the workspace
+  size_t Hint, Vint, norms, sq, delta, xprev, bloc, tf, tb, cf, cb, mc, small;
+  size_t per_prob;
+  size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
+  size_t total;
+};
+
+// hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
+// batch: the three per-slice arrays plus the five per-chunk arrays.  When the
+// full arrays do not fit, slices are processed in segments of G chunks whose
+// per-slice arrays are recomputed for the adjoint pass (sqrt(N)
+// checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
+inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
+  Layout Lo;
+  Lo.D = padded_dim(d);
+  Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
+  if (Lo.L < 1) Lo.L = 1;
+  Lo.P = (N + Lo.L - 1) / Lo.L;
+  const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
+  Lo.G = Lo.P;
+  const double full = (double)B * (3.0 * N + 5.0 * Lo.P) * (double)mat;
+  if (hbm_budget > 0 && full > (double)hbm_budget) {
+    const double avail = (double)hbm_budget / B - 5.0 * Lo.P * (double)mat;
+    const double per_chunk = 3.0 * Lo.L * (double)mat;
+    Lo.G = avail >= per_chunk ? (int)std::min<double>(Lo.P, floor(avail / per_chunk)) : 1;
+  }
+  Lo.W = Lo.G >= Lo.P ? N : std::min(N, Lo.G * Lo.L);
+  size_t o = 0;
+  Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
+  Lo.Vint = o; o = align_up(o + mat);
+  Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
+  Lo.sq = o; o = align_up(o + (size_t)N * 4);
+  Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.tb = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.cb = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.mc = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.small = o; o = align_up(o + 128);
+  Lo.per_prob = o;
+  Lo.desc_bytes = align_up((size_t)B * sizeof(ProbDesc));
+  Lo.scratch = Lo.desc_bytes + (size_t)B * Lo.per_prob;
+  Lo.scratch_bytes = Lo.D == 128 ? (size_t)qoc::kScratchSlots * qoc::kScratchMats * mat : 0;
+  Lo.total = Lo.scratch + Lo.scratch_bytes;
+  return Lo;
+}
+
+
+// Descriptor of one problem whose workspace region starts at pb (layout Lo).
+// Input and output pointers may be null where the launch does not use them.
+inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int N, double dt, int flags,
+                      const double* H0, const double* Hc, const double* u, const double* V, double* F, double* grad,
+                      double* XN) {
+  memset(&P, 0, sizeof P);
+  P.d = d;
+  P.D = Lo.D;
+  P.m = m;
+  P.N = N;
+  P.L = Lo.L;
+  P.P = Lo.P;
+  P.flags = flags;
+  P.dt = dt;
+  P.H0z = H0;
+  P.Hcz = Hc;
+  P.u = u;
+  P.Vz = V;
+  P.grad = grad;
+  P.XN = XN;
+  P.Hint = pb + Lo.Hint;
+  P.Vint = V ? pb + Lo.Vint : nullptr;
+  P.norms = reinterpret_cast<double*>(pb + Lo.norms);
+  P.sq = reinterpret_cast<int*>(pb + Lo.sq);
+  P.delta = pb + Lo.delta;
+  P.xprev = pb + Lo.xprev;
+  P.bloc = pb + Lo.bloc;
+  P.tf = pb + Lo.tf;
+  P.tb = pb + Lo.tb;
+  P.cf = pb + Lo.cf;
+  P.cb = pb + Lo.cb;
+  P.mc = pb + Lo.mc;
+  double* small = reinterpret_cast<double*>(pb + Lo.small);
+  P.g = small;                    // 2 doubles
+  P.F = F ? F : small + 2;        // 1 double
+  P.diag = small + 4;             // 4 doubles
+}
 
 }  // namespace qoc

@@ -54,17 +54,21 @@ __device__ __forceinline__ void split_item(int item, int lo, int count, const in
 struct Items {
   int nprob, total;
   const int* start;
+  const int* slot;  // descriptor index of each problem (engine launches), else identity
   __device__ __forceinline__ explicit Items(const Work& W) {
     if (W.dyn) {
       nprob = W.dyn[0];
       total = W.dyn[1];
       start = W.dyn + 2;
+      slot = W.dyn + 3 + nprob;
     } else {
       nprob = W.nprob;
       total = W.total;
       start = W.start;
+      slot = nullptr;
     }
   }
+  __device__ __forceinline__ int desc(int p) const { return slot ? slot[p] : p; }
 };
 
 template <typename T, int D>
@@ -137,7 +141,7 @@ __global__ __launch_bounds__(256) void k_prep(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, mat;
     split_item(item, 0, W.rg.s_n, I.start, I.nprob, p, mat);
-    prep_one<T, D>(W.descs[p], mat, colmax);
+    prep_one<T, D>(W.descs[I.desc(p)], mat, colmax);
   }
 }
 
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
   for (int item = blockIdx.x * 256 + threadIdx.x; item < I.total; item += gridDim.x * 256) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[p];
+    const ProbDesc& P = W.descs[I.desc(p)];
     double th = P.norms[0];
     for (int j = 0; j < P.m; ++j) th = fma(fabs(P.u[(size_t)j * P.N + k]), P.norms[j + 1], th);
     th *= P.dt;
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, k;
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-  const ProbDesc& P = W.descs[p];
+  const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
   assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0);
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
   split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-  const ProbDesc& P = W.descs[p];
+  const ProbDesc& P = W.descs[I.desc(p)];
   const int k0 = c * P.L;
   const int k1 = min(P.N, k0 + P.L);
   Panel<T, D> S, nxt, acc;
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   const int bwd = blockIdx.y;
   const Items I(W);
   for (int p = blockIdx.x; p < I.nprob; p += gridDim.x) {
-  const ProbDesc& P = W.descs[p];
+  const ProbDesc& P = W.descs[I.desc(p)];
   Panel<T, D> S, nxt, acc;
   const int nc = P.P;
   if (bwd) panel_load(S, reinterpret_cast<const T*>(P.Vint), L); else panel_identity(S, L);
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
   split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-  const ProbDesc& P = W.descs[p];
+  const ProbDesc& P = W.descs[I.desc(p)];
   Panel<T, D> a, b;
   panel_load(a, pf_mat<T, D>(P.cb, c), L);
   panel_to_lds(lds[0], a, L);
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(4 * D) void k_adjoint(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, k;
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-  const ProbDesc& P = W.descs[p];
+  const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
   const int c = k / P.L;
@@ -766,7 +770,7 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[p];
+    const ProbDesc& P = W.descs[I.desc(p)];
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     __syncthreads();
@@ -804,7 +808,7 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int dirs) {
     const int bwd = item % dirs;
     int p, c;
     split_item(item / dirs, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-    const ProbDesc& P = W.descs[p];
+    const ProbDesc& P = W.descs[I.desc(p)];
     const int k0 = c * P.L;
     const int k1 = min(P.N, k0 + P.L);
     Panel<T, 128> acc;
@@ -838,7 +842,7 @@ __global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratc
   const Items I(W);
   for (int item = blockIdx.x; item < I.nprob * dirs; item += gridDim.x) {
     const int bwd = item % dirs;
-    const ProbDesc& P = W.descs[item / dirs];
+    const ProbDesc& P = W.descs[I.desc(item / dirs)];
     const int nc = P.P;
     Panel<T, 128> acc;
     if (!bwd) {
@@ -874,7 +878,7 @@ __global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, c;
     split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-    const ProbDesc& P = W.descs[p];
+    const ProbDesc& P = W.descs[I.desc(p)];
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.cf, c), L);
     Panel<T, 128> acc;
     gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), S0, L, true);
@@ -899,7 +903,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[p];
+    const ProbDesc& P = W.descs[I.desc(p)];
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     const int c = k / P.L;

@@ -43,6 +43,14 @@ EXPORTS = (
     "qoc_stage_timing",
     "qoc_stage_times",
     "qoc_stage_name",
+    "qoc_engine_footprint",
+    "qoc_engine_create",
+    "qoc_engine_destroy",
+    "qoc_engine_submit",
+    "qoc_engine_step",
+    "qoc_engine_poll",
+    "qoc_engine_fetch",
+    "qoc_engine_stats",
     "qoc_last_error",
     "qoc_version",
 )
@@ -98,6 +106,19 @@ def lib() -> ctypes.CDLL:
     L.qoc_stage_times.argtypes = [i32, vp, vp]
     L.qoc_stage_name.argtypes = [i32]
     L.qoc_stage_name.restype = ctypes.c_char_p
+    u64, i64p = ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64)
+    L.qoc_engine_footprint.argtypes = [i32, i32, i32, i32]
+    L.qoc_engine_footprint.restype = u64
+    L.qoc_engine_create.argtypes = [i32, u64, u64, i32, ctypes.POINTER(vp)]
+    L.qoc_engine_destroy.argtypes = [vp]
+    L.qoc_engine_submit.argtypes = [vp, i32, i32, i32, vp, vp, vp, dbl, vp, i64p]
+    L.qoc_engine_step.argtypes = [vp, i32]
+    L.qoc_engine_poll.argtypes = [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_int)]
+    L.qoc_engine_fetch.argtypes = [vp, ctypes.c_int64, vp]
+    L.qoc_engine_stats.argtypes = [vp, i64p, i64p, ctypes.POINTER(u64)]
+    for name in ("qoc_engine_create", "qoc_engine_destroy", "qoc_engine_submit", "qoc_engine_step",
+                 "qoc_engine_poll", "qoc_engine_fetch", "qoc_engine_stats"):
+        getattr(L, name).restype = ctypes.c_int
     L.qoc_last_error.restype = ctypes.c_char_p
     L.qoc_version.restype = ctypes.c_char_p
     for name in ("qoc_stage_timing", "qoc_stage_times", "qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
@@ -289,6 +310,64 @@ class Runner:
 
 
 STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "adjoint")
+
+
+class Engine:
+    """Continuous-batching serving engine of libqoc (see include/qoc.h)."""
+
+    def __init__(self, precision="fp32", pool_bytes=64 << 30, host_bytes=8 << 30, max_active=256):
+        self._p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().qoc_engine_create(self._p, int(pool_bytes), int(host_bytes), int(max_active), ctypes.byref(h)))
+        self._h = h
+        self._shape = {}
+        self._ids = np.zeros(4096, dtype=np.int64)
+        self._F = np.zeros(4096)
+
+    def close(self):
+        if self._h:
+            lib().qoc_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def footprint(precision, d, m, N) -> int:
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        return int(lib().qoc_engine_footprint(p, d, m, N))
+
+    def submit(self, H0, Hc, u, dt, V) -> int:
+        H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
+        d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+        rid = ctypes.c_int64()
+        _check(lib().qoc_engine_submit(self._h, d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V),
+                                       ctypes.byref(rid)))
+        self._shape[rid.value] = (m, N)
+        return rid.value
+
+    def step(self, wait=False):
+        _check(lib().qoc_engine_step(self._h, 1 if wait else 0))
+
+    def poll(self):
+        """[(id, F)] of requests finished since the last poll."""
+        n = ctypes.c_int()
+        _check(lib().qoc_engine_poll(self._h, len(self._ids), _ptr(self._ids), _ptr(self._F), ctypes.byref(n)))
+        return [(int(self._ids[i]), float(self._F[i])) for i in range(n.value)]
+
+    def fetch(self, rid) -> np.ndarray:
+        m, N = self._shape.pop(rid)
+        g = np.empty((m, N))
+        _check(lib().qoc_engine_fetch(self._h, int(rid), _ptr(g)))
+        return g
+
+    def stats(self):
+        q, a, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+        _check(lib().qoc_engine_stats(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(u)))
+        return {"queued": q.value, "active": a.value, "pool_used": u.value}
 
 
 def stage_timing(enable: bool):

@@ -101,3 +101,17 @@ def test_slice_plan_prefers_fewer_products():
     p = make_config(2, N=4)
     plan = qoc.slice_plan(p.H0, p.Hc, 40 * p.u, 20 * p.dt, "fp64", True)
     assert (plan[:, 0] > 0).all()
+
+
+def test_engine_footprint_tracks_the_stored_propagators():
+    """About 3 N D^2 c bytes of stored propagators dominate a request."""
+    L = qoc.lib()
+    for prec, c in (("fp32", 8), ("fp64", 16)):
+        f = qoc.Engine.footprint(prec, 64, 12, 2000)
+        core = 3 * 2000 * 64 * 64 * c
+        assert core < f < 1.2 * core
+        assert qoc.Engine.footprint(prec, 64, 12, 1000) < f
+        # d = 3 is padded to 16: same stored propagators, smaller inputs
+        assert 3 * 100 * 16 * 16 * c < qoc.Engine.footprint(prec, 3, 6, 100) < qoc.Engine.footprint(prec, 16, 6, 100)
+    assert L.qoc_engine_footprint(1, 0, 1, 1) == 0
+    assert L.qoc_engine_footprint(1, 129, 1, 1) == 0

@@ -190,7 +190,8 @@ def poisson_trace(n: int, rate: float, seed: int = 5, N_range=(100, 2000)):
     Returns a list of dicts {index, t_arrival, d, N}; d is drawn with
     SERVE_WEIGHTS and N uniformly from N_range (inclusive)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
-    gaps = rng.exponential(1.0 / rate, size=n) if rate > 0 else np.zeros(n)
+    unit = rng.exponential(1.0, size=n)          # drawn for any rate, so shapes never depend on it
+    gaps = unit / rate if rate > 0 else np.zeros(n)   # rate <= 0: everything arrives at t = 0
     t = np.cumsum(gaps) - (gaps[0] if n else 0.0)
     ds = rng.choice(np.array(SERVE_DIMS), size=n, p=np.array(SERVE_WEIGHTS))
     Ns = rng.integers(N_range[0], N_range[1] + 1, size=n)
