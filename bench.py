@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="before timing, run one plain device-to-device copy of this many GiB "
+                         "(a reference of known size for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -108,6 +111,14 @@ def main():
     from workloads import make_batch
 
     torch.cuda.init()
+    if args.copy_gib > 0:
+        n = int(args.copy_gib * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     B = args.batch
     problems = make_batch(CFG, B)
     d, m, N = problems[0].d, problems[0].m, problems[0].N

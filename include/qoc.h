@@ -67,10 +67,18 @@ typedef struct {
                              When the N + chunk arrays exceed it, slices are
                              processed in checkpoint segments and recomputed
                              for the gradient pass (same results, more work). */
-  double reunitarise_tol; /* reserved; < 0 disables */
+  double reunitarise_tol; /* reduced precision, d <= 64: every chunk product S of the
+                             scans is checked in FP64, r = |S^dag S - I|_F, and gets one
+                             Newton-Schulz step S (3I - S^dag S)/2 when r exceeds it.
+                             0 = default (1e-6 FP32, 1e-4 BF16X3); < 0 disables;
+                             never applied in FP64. */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
   int32_t chunk;          /* slices per scan chunk; 0 = ceil(sqrt(N)) */
   int32_t reserved;
+  double* diagnostics;    /* optional, 4 doubles per problem (device memory for _dev calls,
+                             host memory for host calls): [0] |X_N^dag X_N - I|_F,
+                             [1] largest chunk residual r, [2] number of Newton-Schulz
+                             steps (integer stored as uint64 bits), [3] unused */
 } qoc_options; /* pass NULL for all defaults */
 
 /* Fill *opt with the defaults listed above. */

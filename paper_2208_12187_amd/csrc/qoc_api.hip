@@ -133,6 +133,13 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
   return e;
 }
 
+// Re-unitarisation threshold of a call: off in FP64 and above d = 64.
+double reun_tol(const qoc_options& o) {
+  if (o.precision == QOC_FP64 || o.reunitarise_tol < 0) return -1.0;
+  if (o.reunitarise_tol > 0) return o.reunitarise_tol;
+  return o.precision == QOC_BF16X3 ? 1e-4 : 1e-6;
+}
+
 // Enqueue the path for a uniform batch whose inputs and outputs are in
 // device memory.  flags: qoc::RUN_* bits.
 int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt, const void* V,
@@ -153,13 +160,15 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   char* base = static_cast<char*>(ws);
   std::vector<ProbDesc> descs(B);
   const size_t dd = (size_t)d * d;
+  const double tol = reun_tol(opt);
   for (int b = 0; b < B; ++b) {
     char* pb = base + Lo.desc_bytes + (size_t)b * Lo.per_prob;
     fill_desc(descs[b], Lo, pb, d, m, N, dt, flags, static_cast<const double*>(H0) + 2 * dd * b,
               static_cast<const double*>(Hc) + 2 * dd * m * b, static_cast<const double*>(u) + (size_t)m * N * b,
               V ? static_cast<const double*>(V) + 2 * dd * b : nullptr, F ? static_cast<double*>(F) + b : nullptr,
               grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr,
-              XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr);
+              XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr, tol,
+              opt.diagnostics ? opt.diagnostics + 4 * b : nullptr);
   }
   hipStream_t st = static_cast<hipStream_t>(opt.stream);
   hipError_t e = hipMemcpyAsync(base, descs.data(), (size_t)B * sizeof(ProbDesc), hipMemcpyHostToDevice, st);
@@ -224,6 +233,7 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
   void* dgrad = grad ? bufs.alloc((size_t)m * N * 8) : nullptr;
   void* dXN = XN ? bufs.alloc(dd * 16) : nullptr;
   void* dws = bufs.alloc(ws_bytes);
+  void* ddiag = opt.diagnostics ? bufs.alloc(4 * sizeof(double)) : nullptr;
   if (!dH0 || !dHc || !du || (V && !dV) || !dF || (grad && !dgrad) || (XN && !dXN) || !dws)
     return fail(QOC_ERR_OOM, "device allocation of %zu workspace bytes failed", ws_bytes);
   hipStream_t st = static_cast<hipStream_t>(opt.stream);
@@ -234,6 +244,7 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
   if (V) e = e ? e : hipMemcpyAsync(dV, V, dd * 16, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "upload: %s", hipGetErrorString(e));
   qoc_options o2 = opt;
+  o2.diagnostics = static_cast<double*>(ddiag);
   rc = run_dev(1, d, m, N, dH0, dHc, du, dt, dV, dF, dgrad, dXN, dws, ws_bytes, &o2, flags);
   if (rc) return rc;
   e = hipStreamSynchronize(st);
@@ -241,6 +252,7 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
   if (F) e = e ? e : hipMemcpy(F, dF, 8, hipMemcpyDeviceToHost);
   if (grad) e = e ? e : hipMemcpy(grad, dgrad, (size_t)m * N * 8, hipMemcpyDeviceToHost);
   if (XN) e = e ? e : hipMemcpy(XN, dXN, dd * 16, hipMemcpyDeviceToHost);
+  if (ddiag) e = e ? e : hipMemcpy(opt.diagnostics, ddiag, 4 * sizeof(double), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(QOC_ERR_DEVICE, "download: %s", hipGetErrorString(e));
   return QOC_OK;
 }
@@ -346,7 +358,8 @@ void qoc_default_options(qoc_options* opt) {
   opt->precision = QOC_FP64;
   opt->validate = 0;
   opt->hbm_budget = 0;
-  opt->reunitarise_tol = -1.0;
+  opt->reunitarise_tol = 0.0;
+  opt->diagnostics = nullptr;
   opt->stream = nullptr;
   opt->chunk = 0;
 }

@@ -41,7 +41,9 @@ struct ProbDesc {
   void* cb;           // P PF matrices: backward carry out of each chunk
   void* mc;           // P PF matrices: cb[c] cf[c]^dag
   double* g;          // complex128 Tr(V^dag X_N)
-  double* diag;       // [0] = ||X_N^dag X_N - I||_F
+  double* diag;       // [0] ||X_N^dag X_N - I||_F; [1] largest chunk residual (FP64
+                      // bits, atomic max); [2] re-unitarisation steps (uint64 count)
+  double reun_tol;    // re-unitarisation threshold for chunk totals, < 0: off
 };
 
 enum : int {
@@ -180,7 +182,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
 // Input and output pointers may be null where the launch does not use them.
 inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int N, double dt, int flags,
                       const double* H0, const double* Hc, const double* u, const double* V, double* F, double* grad,
-                      double* XN) {
+                      double* XN, double reun_tol = -1.0, double* diag = nullptr) {
   memset(&P, 0, sizeof P);
   P.d = d;
   P.D = Lo.D;
@@ -211,7 +213,8 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   double* small = reinterpret_cast<double*>(pb + Lo.small);
   P.g = small;                    // 2 doubles
   P.F = F ? F : small + 2;        // 1 double
-  P.diag = small + 4;             // 4 doubles
+  P.diag = diag ? diag : small + 4;  // 4 doubles
+  P.reun_tol = reun_tol;
 }
 
 }  // namespace qoc

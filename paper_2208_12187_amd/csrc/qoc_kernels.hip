@@ -84,6 +84,10 @@ __device__ __forceinline__ T* pf_mat(void* base, int i) {
 template <typename T, int D>
 __device__ __forceinline__ void prep_one(const ProbDesc& P, int mat, double* colmax) {
   const int d = P.d, m = P.m;
+  if (mat == 0 && threadIdx.x == 0) {
+    P.diag[1] = 0.0;
+    P.diag[2] = 0.0;
+  }
   if (mat <= m) {
     const double* src = mat == 0 ? P.H0z : P.Hcz + (size_t)(mat - 1) * 2 * d * d;
     T* dst = reinterpret_cast<T*>(P.Hint) + (size_t)mat * 2 * D * D;
@@ -361,6 +365,82 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   }
 }
 
+// ---------------------------------------------------------------- re-unitarisation
+
+// Check of a chunk product S (FP32 panel) in FP64: r = |S^dag S - I|_F over
+// the d x d block, recorded as the largest residual of the problem.  When
+// r > tol, one Newton-Schulz polar step S <- S (3I - S^dag S) / 2 (Higham
+// 1986) moves S back towards the unitary group; the steps are counted.  The
+// FP32 panel is moved into the FP64 register layout (and back) through LDS,
+// which must hold one FP64 matrix.
+template <int D>
+__device__ __forceinline__ void reunitarise(const ProbDesc& P, Panel<float, D>& S, void* lds_raw, double* red,
+                                            const Lane& L) {
+  constexpr int NW = D / 16;
+  double* M = static_cast<double*>(lds_raw);
+  double* Mi = M + D * Mat<double, D>::SD;
+  const int d = P.d;
+  __syncthreads();
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int off = lds_off<double, D>(16 * rb + Prec<float>::rowmap(r, L.g), 16 * L.w + L.c16);
+      M[off] = (double)S.re[rb][r];
+      Mi[off] = (double)S.im[rb][r];
+    }
+  __syncthreads();
+  Panel<double, D> Sd, G;
+  panel_from_lds(Sd, M, L);
+  __syncthreads();
+  panel_to_lds_ct(M, Sd, L);
+  __syncthreads();
+  cgemm(G, M, Sd, L, true);  // G = S^dag S
+  double e2 = 0;
+#pragma unroll
+  for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + Prec<double>::rowmap(r, L.g), col = 16 * L.w + L.c16;
+      if (row < d && col < d) {
+        const double xr = G.re[rb][r] - (row == col ? 1.0 : 0.0), xi = G.im[rb][r];
+        e2 += xr * xr + xi * xi;
+      }
+    }
+  e2 = wave_sum(e2);
+  if (L.lane == 0) red[L.w] = e2;
+  __syncthreads();
+  double tot = 0;
+  for (int w = 0; w < NW; ++w) tot += red[w];
+  const double res = sqrt(tot);
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&P.diag[1]), (unsigned long long)__double_as_longlong(res));
+  if (res > P.reun_tol) {
+    // T = 3I - G, S <- S T / 2
+    panel_scale(G, -1.0);
+    panel_add_identity(G, L, 3.0);
+    __syncthreads();
+    panel_to_lds(M, Sd, L);
+    __syncthreads();
+    Panel<double, D> Sn;
+    cgemm(Sn, M, G, L, true);
+    panel_scale(Sn, 0.5);
+    __syncthreads();
+    panel_to_lds(M, Sn, L);
+    __syncthreads();
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int off = lds_off<double, D>(16 * rb + Prec<float>::rowmap(r, L.g), 16 * L.w + L.c16);
+        S.re[rb][r] = (float)M[off];
+        S.im[rb][r] = (float)Mi[off];
+      }
+    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.diag[2]), 1ull);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------- chunked scans
 
 // One workgroup per (chunk, direction).  Forward (blockIdx.y = 0): running
@@ -371,6 +451,7 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
+  __shared__ double red[D / 16];
   Lane L;
   const int bwd = blockIdx.y;
   const Items I(W);
@@ -395,6 +476,10 @@ __global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
     Ops::gemm(acc, buf, S, L, true);
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
+  }
+  if constexpr (sizeof(T) == 4) {
+    static_assert(2 * Ops::BYTES >= (int)sizeof(double) * Mat<double, D>::LDS_ELEMS, "LDS too small");
+    if (P.reun_tol >= 0) reunitarise<D>(P, S, &lds[0][0], red, L);
   }
   panel_store(pf_mat<T, D>(bwd ? P.tb : P.tf, c), S, L);
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop

@@ -71,6 +71,7 @@ class Options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("chunk", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("diagnostics", ctypes.c_void_p),
     ]
 
 

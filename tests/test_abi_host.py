@@ -32,7 +32,7 @@ def test_every_declared_symbol_is_exported():
 def test_version_and_defaults():
     assert "libqoc" in qoc.version()
     o = qoc.options()
-    assert o.precision == qoc.FP64 and o.chunk == 0 and o.reunitarise_tol < 0
+    assert o.precision == qoc.FP64 and o.chunk == 0 and o.reunitarise_tol == 0.0 and not o.diagnostics
 
 
 def _err(fn, *a):

@@ -104,3 +104,46 @@ def test_differentiation_workload_full_size(gpu_lib):
         fd = (qoc.fidelity(p.H0, p.Hc, up, p.dt, p.V, "fp64", hbm_budget=budget)
               - qoc.fidelity(p.H0, p.Hc, dn, p.dt, p.V, "fp64", hbm_budget=budget)) / (2 * h)
         assert abs(fd - grad[j, k]) <= 1e-4 * max(abs(grad[j, k]), 0.1 * gmax), (j, k, fd, grad[j, k])
+
+
+def _grad_diag(p, prec, tol):
+    """Host-entry gradient with the diagnostics block returned."""
+    import ctypes
+    from paper_2208_12187_amd import qoc
+
+    H0, Hc, u, V = (np.ascontiguousarray(x) for x in (p.H0, p.Hc, p.u, p.V))
+    F = np.zeros(1)
+    grad = np.empty((p.m, p.N))
+    diag = np.zeros(4)
+    o = qoc.options(prec)
+    o.reunitarise_tol = tol
+    o.diagnostics = diag.ctypes.data
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rc = qoc.lib().qoc_gradient(p.d, p.m, p.N, ptr(H0), ptr(Hc), ptr(u), p.dt, ptr(V), ptr(F), ptr(grad),
+                                ctypes.byref(o))
+    assert rc == 0, qoc.lib().qoc_last_error()
+    return F[0], grad, diag[0], diag[1], int(diag[2:3].view(np.uint64)[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_reunitarisation_check_and_step(gpu_lib, prec):
+    """Chunk residuals are measured in FP64 and reported; forcing a
+    Newton-Schulz step on every chunk keeps the result within tolerance and
+    does not worsen the unitarity of X_N."""
+    p = make_config(3, N=400)
+    ref = oracle.grape_ref(p)
+    F0, g0, rX0, rmax0, n0 = _grad_diag(p, prec, -1.0)   # check off
+    F1, g1, rX1, rmax1, n1 = _grad_diag(p, prec, 0.0)    # default threshold
+    F2, g2, rX2, rmax2, n2 = _grad_diag(p, prec, 1e-14)  # every chunk
+    print(f"[features] {prec}: residual X_N off={rX0:.2e} default={rX1:.2e} forced={rX2:.2e}, "
+          f"max chunk residual {rmax1:.2e}, steps default={n1} forced={n2}", flush=True)
+    L = int(np.ceil(np.sqrt(p.N)))
+    P = -(-p.N // L)
+    assert n0 == 0 and rmax0 == 0.0
+    assert 0 < rmax1 < 1e-3
+    assert n2 == 2 * P
+    assert rX2 <= 2 * rX0 + 1e-12
+    gmax = np.max(np.abs(ref["grad"]))
+    for F, g in ((F0, g0), (F1, g1), (F2, g2)):
+        assert abs(F - ref["F"]) <= 1e-5
+        assert np.max(np.abs(g - ref["grad"])) <= 1e-4 * gmax
