@@ -25,6 +25,7 @@ if ROOT not in sys.path:
 METRIC = "GRAPE slice-steps/s (fwd+grad, d=64) vs plain FP64; p50/p99 request latency"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 CFG = 3  # 6-qubit Ising chain, d = 64
+WORKLOADS = {2: "4-qubit Heisenberg chain", 3: "6-qubit Ising chain", 4: "7-qubit Heisenberg chain"}
 
 
 def slice_flops(plan: np.ndarray, d: int, m: int) -> dict:
@@ -67,6 +68,25 @@ def time_runner(qoc, torch, runner, batch, steps, warmup):
     return {"ms_per_step": ms, "wall_s": wall, "stages": stages, "F": F.cpu().numpy(), "grad": grad}
 
 
+def measured_traffic(kernel_avg_ms):
+    """HBM bytes per launch of the adjoint kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a
+    plain 1 GiB copy), or None when the kernel sources changed since then."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_adjoint_counters.json")
+    csrc = os.path.join(ROOT, "paper_2208_12187_amd", "csrc")
+    try:
+        with open(path) as f:
+            z = json.load(f)
+        src = b"".join(open(os.path.join(csrc, n), "rb").read() for n in sorted(os.listdir(csrc)))
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != z.get("csrc_sha256"):
+        return None
+    return (z["fetch_kib"] * z["fetch_scale"] + z["write_kib"] * z["write_scale"]) * 1024.0
+
+
 def cpu_baseline():
     """The CPU oracle on one full configuration-3 problem (N = 2000 slices)."""
     import oracle
@@ -92,6 +112,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--config", type=int, default=CFG, choices=[2, 3, 4],
+                    help="workload: 3 = 6-qubit Ising d=64 (the headline), 2 = d=16, 4 = d=128")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--no-bf16", action="store_true", help="skip the split-BF16 leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
@@ -120,7 +142,7 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     B = args.batch
-    problems = make_batch(CFG, B)
+    problems = make_batch(args.config, B)
     d, m, N = problems[0].d, problems[0].m, problems[0].N
     batch = qoc.Batch.from_problems(problems)
     plans = {pr: np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, pr, True) for p in problems])
@@ -144,9 +166,11 @@ def main():
     adj_flops = flops[args.precision]["adjoint"]
     achieved = adj_flops / adj_avg_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    traffic = measured_traffic(adj_ms / max(adj_n, 1)) if (args.precision == "fp32" and args.config == CFG
+                                                          and B == 32) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None, "kernel": "k_adjoint",
-                "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4)}
+                "frac": round(achieved / peak, 4), "traffic": None if traffic is None else round(traffic),
+                "kernel": "k_adjoint", "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4)}
     total_flops = sum(flops[args.precision].values())
     stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in head["stages"].items() if v[1]}
 
@@ -159,7 +183,7 @@ def main():
                          "path_tflops": round(sum(flops["fp64"].values()) / (f64["ms_per_step"] / 1e3) / 1e12, 2)}
         extra["speedup_vs_fp64"] = round(value / v64, 3)
         extra["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(head["F"] - f64["F"])))
-    if not args.no_bf16 and args.precision != "bf16x3":
+    if not args.no_bf16 and args.precision != "bf16x3" and 16 < d <= 64:
         b3 = leg("bf16x3", args.steps)
         v3 = B * N / (b3["ms_per_step"] / 1e3)
         adj3_ms, adj3_n = b3["stages"]["adjoint"]
@@ -194,8 +218,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"6-qubit Ising chain GRAPE fwd+grad, d={d}, m={m}, N={N}, dt=0.002, "
-                               f"batch of {B} seeded problems",
+        "config": {"workload": f"{WORKLOADS[args.config]} GRAPE fwd+grad, d={d}, m={m}, N={N}, "
+                               f"dt={problems[0].dt}, batch of {B} seeded problems",
                    "d": d, "m": m, "N": N, "batch": B, "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": None if cpu is None else {k: (round(v, 2) if isinstance(v, float) else v)

@@ -22,15 +22,27 @@ namespace qoc {
 
 typedef short s8v __attribute__((ext_vector_type(8)));
 typedef short s4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ unsigned bf16_rne(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+// Split two FP32 values at once: hi = bf16(x) with round to nearest even
+// (one v_cvt_pk_bf16_f32 on gfx950), lo = bf16(x - hi).  Element 0 sits in
+// the low 16 bits of the packed results.
+__device__ __forceinline__ void bf16_split2(float x0, float x1, unsigned& hi, unsigned& lo) {
+  const f2v v = {x0, x1};
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2v));
+  const f2v r = {x0 - __uint_as_float(hi << 16), x1 - __uint_as_float(hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2v));
 }
 
 __device__ __forceinline__ void bf16_split(float x, unsigned& hi, unsigned& lo) {
-  hi = bf16_rne(x);
-  lo = bf16_rne(x - __uint_as_float(hi << 16));
+  unsigned h, l;
+  bf16_split2(x, 0.0f, h, l);
+  hi = h & 0xffffu;
+  lo = l & 0xffffu;
 }
 
 __device__ __forceinline__ float bf16_join(unsigned short hi, unsigned short lo) {
@@ -68,10 +80,24 @@ struct Bf3Ops {
   }
 
   __device__ static __forceinline__ void store(void* lds, const Panel<float, D>& P, const Lane& L) {
+    const int pc = phys(16 * L.w + L.c16);
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) put(lds, 16 * rb + 4 * L.g + r, 16 * L.w + L.c16, P.re[rb][r], P.im[rb][r]);
+      for (int r = 0; r < 4; r += 2) {
+        unsigned rh, rl, ih, il;
+        bf16_split2(P.re[rb][r], P.re[rb][r + 1], rh, rl);
+        bf16_split2(P.im[rb][r], P.im[rb][r + 1], ih, il);
+        const int o0 = (16 * rb + 4 * L.g + r) * SB + pc, o1 = o0 + SB;
+        plane(lds, 0)[o0] = (unsigned short)rh;
+        plane(lds, 0)[o1] = (unsigned short)(rh >> 16);
+        plane(lds, 1)[o0] = (unsigned short)rl;
+        plane(lds, 1)[o1] = (unsigned short)(rl >> 16);
+        plane(lds, 2)[o0] = (unsigned short)ih;
+        plane(lds, 2)[o1] = (unsigned short)(ih >> 16);
+        plane(lds, 3)[o0] = (unsigned short)il;
+        plane(lds, 3)[o1] = (unsigned short)(il >> 16);
+      }
   }
 
   // Conjugate transpose: M^dag[16w + c16][16 rb + 4g + r]; the four r are
@@ -80,21 +106,21 @@ struct Bf3Ops {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
       const int off = (16 * L.w + L.c16) * SB + phys(16 * rb + 4 * L.g);
-      s4v rh, rl, ih, il;
+      u2v rh, rl, ih, il;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < 4; r += 2) {
         unsigned h, l;
-        bf16_split(P.re[rb][r], h, l);
-        rh[r] = (short)h;
-        rl[r] = (short)l;
-        bf16_split(-P.im[rb][r], h, l);
-        ih[r] = (short)h;
-        il[r] = (short)l;
+        bf16_split2(P.re[rb][r], P.re[rb][r + 1], h, l);
+        rh[r / 2] = h;
+        rl[r / 2] = l;
+        bf16_split2(-P.im[rb][r], -P.im[rb][r + 1], h, l);
+        ih[r / 2] = h;
+        il[r / 2] = l;
       }
-      *reinterpret_cast<s4v*>(plane(lds, 0) + off) = rh;
-      *reinterpret_cast<s4v*>(plane(lds, 1) + off) = rl;
-      *reinterpret_cast<s4v*>(plane(lds, 2) + off) = ih;
-      *reinterpret_cast<s4v*>(plane(lds, 3) + off) = il;
+      *reinterpret_cast<u2v*>(plane(lds, 0) + off) = rh;
+      *reinterpret_cast<u2v*>(plane(lds, 1) + off) = rl;
+      *reinterpret_cast<u2v*>(plane(lds, 2) + off) = ih;
+      *reinterpret_cast<u2v*>(plane(lds, 3) + off) = il;
     }
   }
 
@@ -140,21 +166,23 @@ struct Bf3Ops {
     const int base = L.c16 * SB + 8 * L.g;
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-      s8v brh, brl, bih, bil, nih, nil;
+      u4v rh, rl, ih, il, nh, nl;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float xr = j < 4 ? P.re[2 * t][j] : P.re[2 * t + 1][j - 4];
-        const float xi = j < 4 ? P.im[2 * t][j] : P.im[2 * t + 1][j - 4];
+      for (int jp = 0; jp < 4; ++jp) {
+        const int rb = 2 * t + (jp >> 1), r = 2 * (jp & 1);
         unsigned h, l;
-        bf16_split(xr, h, l);
-        brh[j] = (short)h;
-        brl[j] = (short)l;
-        bf16_split(xi, h, l);
-        bih[j] = (short)h;
-        bil[j] = (short)l;
-        nih[j] = (short)(h ^ 0x8000u);
-        nil[j] = (short)(l ^ 0x8000u);
+        bf16_split2(P.re[rb][r], P.re[rb][r + 1], h, l);
+        rh[jp] = h;
+        rl[jp] = l;
+        bf16_split2(P.im[rb][r], P.im[rb][r + 1], h, l);
+        ih[jp] = h;
+        il[jp] = l;
+        nh[jp] = h ^ 0x80008000u;
+        nl[jp] = l ^ 0x80008000u;
       }
+      const s8v brh = __builtin_bit_cast(s8v, rh), brl = __builtin_bit_cast(s8v, rl);
+      const s8v bih = __builtin_bit_cast(s8v, ih), bil = __builtin_bit_cast(s8v, il);
+      const s8v nih = __builtin_bit_cast(s8v, nh), nil = __builtin_bit_cast(s8v, nl);
       s8v a[2][4];
       {
         const int off = base + 32 * t;

@@ -566,8 +566,14 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 //  4. s squarings: [[I + D1, Q], [0, I + D1]]^2 gives D1 <- 2 D1 + D1^2 and
 //     Q <- 2Q + D1 Q + Q D1.  Z_k = Q.
 //  5. T_j = Tr(Z_k^dag Hc[j]) in FP64, grad = (2 dt / d^2) Im(conj(g) T_j).
+// Two workgroups per CU (two waves per SIMD) where the LDS allows it, so
+// that one workgroup's LDS and VALU work overlaps the other's MFMAs.
+template <typename T, int D>
+constexpr int kAdjWaves = (sizeof(T) == 4 && D <= 64) ? 2 : 1;
+
 template <typename T, int D, typename Ops, bool PERSIST>
-__global__ __launch_bounds__(4 * D) void k_adjoint(Work W) {
+__global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves<T, D>)))
+void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
   __shared__ double red[2][2 * NW];

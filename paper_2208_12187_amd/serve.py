@@ -19,8 +19,8 @@ import numpy as np
 from . import qoc
 
 
-def replay(problems, arrivals, precision="fp32", max_active=256, pool_bytes=96 << 30, host_bytes=16 << 30,
-           keep_grad=False, engine=None):
+def replay(problems, arrivals, precision="fp32", max_active=256, pool_bytes=96 << 30, host_bytes=8 << 30,
+           keep_grad=False, engine=None, progress=None):
     """Submit problems[i] at arrivals[i] seconds after the start (all at once if
     every arrival is 0) and collect results.  Returns a dict with per-request
     latency, F (and gradients when keep_grad), makespan and throughput."""
@@ -54,6 +54,8 @@ def replay(problems, arrivals, precision="fp32", max_active=256, pool_bytes=96 <
                 if keep_grad:
                     grads[i] = g
                 done += 1
+                if progress and done % progress == 0:
+                    print(f"[serve] {done}/{n} done at {t:.2f} s", flush=True)
             if not got and nxt < n:
                 gap = arrivals[order[nxt]] - (time.perf_counter() - t0)
                 if gap > 2e-4:
@@ -104,15 +106,20 @@ def main(argv=None):
     ap.add_argument("--max-active", type=int, default=256)
     ap.add_argument("--seed", type=int, default=5)
     args = ap.parse_args(argv)
+    t0 = time.perf_counter()
     trace, problems = build_requests(args.requests, args.seed)
     n = len(problems)
+    print(f"[serve] built {n} requests in {time.perf_counter() - t0:.1f} s", flush=True)
     zero = np.zeros(n)
-    cap = replay(problems, zero, args.precision, args.max_active)
+    prog = max(1, n // 8)
+    cap = replay(problems, zero, args.precision, args.max_active, progress=prog)
     capacity = cap["requests_per_s"]
     rate = args.load * capacity
+    print(f"[serve] capacity {capacity:.1f} req/s; replaying at {rate:.1f} req/s", flush=True)
     arr = poisson_arrivals(n, rate, args.seed)
-    mix = replay(problems, arr, args.precision, args.max_active)
-    alone = replay(problems, arr, args.precision, 1)
+    mix = replay(problems, arr, args.precision, args.max_active, progress=prog)
+    print(f"[serve] batched: {summary(mix)}", flush=True)
+    alone = replay(problems, arr, args.precision, 1, progress=prog)
     out = {"requests": n, "precision": args.precision, "capacity_req_per_s": round(capacity, 1),
            "capacity_slice_steps_per_s": round(cap["slice_steps_per_s"], 1),
            "arrival_rate_req_per_s": round(rate, 1), "batched": summary(mix), "one_at_a_time": summary(alone),
