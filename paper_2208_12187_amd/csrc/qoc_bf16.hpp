@@ -79,6 +79,30 @@ struct Bf3Ops {
     plane(lds, 3)[off] = (unsigned short)l;
   }
 
+  // Four consecutive columns col..col+3 of one row (col a multiple of 4):
+  // contiguous after phys(), one 8-byte write per plane.
+  __device__ static __forceinline__ void put4(void* lds, int row, int col, f4 re, f4 im) {
+    const int off = row * SB + phys(col);
+    u2v rh, rl, ih, il;
+    unsigned h, l;
+    bf16_split2(re[0], re[1], h, l);
+    rh[0] = h;
+    rl[0] = l;
+    bf16_split2(re[2], re[3], h, l);
+    rh[1] = h;
+    rl[1] = l;
+    bf16_split2(im[0], im[1], h, l);
+    ih[0] = h;
+    il[0] = l;
+    bf16_split2(im[2], im[3], h, l);
+    ih[1] = h;
+    il[1] = l;
+    *reinterpret_cast<u2v*>(plane(lds, 0) + off) = rh;
+    *reinterpret_cast<u2v*>(plane(lds, 1) + off) = rl;
+    *reinterpret_cast<u2v*>(plane(lds, 2) + off) = ih;
+    *reinterpret_cast<u2v*>(plane(lds, 3) + off) = il;
+  }
+
   __device__ static __forceinline__ void store(void* lds, const Panel<float, D>& P, const Lane& L) {
     const int pc = phys(16 * L.w + L.c16);
 #pragma unroll

@@ -349,6 +349,19 @@ struct StdOps {
     p[off] = re;
     p[D * Mat<T, D>::SD + off] = im;
   }
+  // Four consecutive columns col..col+3 of one row (col a multiple of 4).
+  __device__ static __forceinline__ void put4(void* lds, int row, int col, typename Prec<T>::v4 re,
+                                              typename Prec<T>::v4 im) {
+    T* p = static_cast<T*>(lds);
+    if constexpr (sizeof(T) == 4) {
+      const int off = lds_off<T, D>(row, col);
+      Prec<T>::st4(p + off, re);
+      Prec<T>::st4(p + D * Mat<T, D>::SD + off, im);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) put(lds, row, col + i, re[i], im[i]);
+    }
+  }
   __device__ static __forceinline__ void store(void* lds, const Panel<T, D>& P, const Lane& L) {
     panel_to_lds(static_cast<T*>(lds), P, L);
   }

@@ -172,32 +172,33 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
 template <typename T, int D, typename Ops>
 __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn) {
-  constexpr int NT = Mat<T, D>::NT;
-  constexpr int EPT = D * D / NT;
+  // Thread t owns the D/4 consecutive elements [t D/4, (t+1) D/4) of one row,
+  // read with 16-byte loads (coalesced across the workgroup) and written to
+  // LDS four columns at a time.
+  using v4 = typename Prec<T>::v4;
+  constexpr int EPT = D / 4;
+  constexpr int NV = EPT / 4;
   const T* H = reinterpret_cast<const T*>(P.Hint);
-  T hr[EPT], hi[EPT];
+  const int e0 = threadIdx.x * EPT;
+  v4 hr[NV], hi[NV];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    int e = threadIdx.x + i * NT;
-    hr[i] = H[e];
-    hi[i] = H[D * D + e];
+  for (int v = 0; v < NV; ++v) {
+    hr[v] = Prec<T>::ld4(H + e0 + 4 * v);
+    hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * v);
   }
   for (int j = 0; j < P.m; ++j) {
     const T uj = (T)P.u[(size_t)j * P.N + k];
     const T* Hj = H + (size_t)(j + 1) * 2 * D * D;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      int e = threadIdx.x + i * NT;
-      hr[i] += uj * Hj[e];
-      hi[i] += uj * Hj[D * D + e];
+    for (int v = 0; v < NV; ++v) {
+      hr[v] += uj * Prec<T>::ld4(Hj + e0 + 4 * v);
+      hi[v] += uj * Prec<T>::ld4(Hj + D * D + e0 + 4 * v);
     }
   }
   const T f = (T)(sgn * c);
+  const int row = e0 / D, col = e0 % D;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    int e = threadIdx.x + i * NT;
-    Ops::put(lds, e / D, e % D, f * hi[i], -f * hr[i]);  // -i f (hr + i hi) = f hi - i f hr
-  }
+  for (int v = 0; v < NV; ++v) Ops::put4(lds, row, col + 4 * v, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
 }
 
 __device__ __forceinline__ void unpack_sq(int sq, int& s, int& q, int& qb) {
@@ -285,7 +286,13 @@ __device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel
 }
 
 // Z = Z_k (panel): T_j = Tr(Z^dag Hc[j]) with FP64 accumulation and
-// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  red: 2 x 2 * D/16 doubles of LDS.
+// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  Controls are taken in groups
+// of kEpiGroup: every wavefront reduces its partial sums of the group, one
+// barrier publishes them, and one thread per control finishes the sum over
+// wavefronts.  red: 2 x kEpiGroup x 2 x D/16 doubles of LDS (double-buffered
+// by group).
+constexpr int kEpiGroup = 16;
+
 template <typename T, int D>
 __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
                                                   double* red) {
@@ -293,29 +300,39 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
   const T* H = reinterpret_cast<const T*>(P.Hint);
   const double gr = P.g[0], gi = P.g[1];
   const double pref = 2.0 * P.dt / ((double)P.d * P.d);
-  for (int j = 0; j < P.m; ++j) {
-    const T* Hr = H + (size_t)(j + 1) * 2 * D * D;
-    const T* Hi = Hr + D * D;
-    double tr = 0, ti = 0;
+  for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
+    const int nj = min(kEpiGroup, P.m - j0);
+    double* rg = red + (grp & 1) * kEpiGroup * 2 * NW;
+    for (int jj = 0; jj < nj; ++jj) {
+      const T* Hr = H + (size_t)(j0 + jj + 1) * 2 * D * D;
+      const T* Hi = Hr + D * D;
+      double tr = 0, ti = 0;
 #pragma unroll
-    for (int rb = 0; rb < D / 16; ++rb)
+      for (int rb = 0; rb < D / 16; ++rb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
-        double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
-        double hr = (double)Hr[e], hi = (double)Hi[e];
-        tr += zr * hr + zi * hi;  // conj(z) h
-        ti += zr * hi - zi * hr;
+        for (int r = 0; r < 4; ++r) {
+          int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
+          double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
+          double hr = (double)Hr[e], hi = (double)Hi[e];
+          tr += zr * hr + zi * hi;  // conj(z) h
+          ti += zr * hi - zi * hr;
+        }
+      tr = wave_sum(tr);
+      ti = wave_sum(ti);
+      if (L.lane == 0) {
+        rg[(jj * NW + L.w) * 2] = tr;
+        rg[(jj * NW + L.w) * 2 + 1] = ti;
       }
-    tr = wave_sum(tr);
-    ti = wave_sum(ti);
-    double* rj = red + (j & 1) * 2 * NW;
-    if (L.lane == 0) { rj[2 * L.w] = tr; rj[2 * L.w + 1] = ti; }
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if ((int)threadIdx.x < nj) {
+      const int jj = threadIdx.x;
       double a = 0, b = 0;
-      for (int w = 0; w < NW; ++w) { a += rj[2 * w]; b += rj[2 * w + 1]; }
-      P.grad[(size_t)j * P.N + k] = pref * (gr * b - gi * a);
+      for (int w = 0; w < NW; ++w) {
+        a += rg[(jj * NW + w) * 2];
+        b += rg[(jj * NW + w) * 2 + 1];
+      }
+      P.grad[(size_t)(j0 + jj) * P.N + k] = pref * (gr * b - gi * a);
     }
   }
 }
@@ -576,7 +593,7 @@ __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves
 void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
-  __shared__ double red[2][2 * NW];
+  __shared__ double red[2 * kEpiGroup * 2 * NW];
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -649,7 +666,7 @@ void k_adjoint(Work W) {
   }
 
   // 5. inner products with the controls (FP64), then the gradient
-  gradient_epilogue<T, D>(P, k, A2, L, &red[0][0]);
+  gradient_epilogue<T, D>(P, k, A2, L, red);
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
   }
@@ -982,7 +999,7 @@ __global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
 template <typename T>
 __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
-  __shared__ double red[2 * 2 * 8];
+  __shared__ double red[2 * kEpiGroup * 2 * 8];
   Lane L;
   T* S0 = slot_mat<T>(scratch, 0);
   T* S1 = slot_mat<T>(scratch, 1);
