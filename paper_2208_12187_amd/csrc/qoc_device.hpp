@@ -332,6 +332,33 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums each of V values of every lane over the wavefront in log2(V) halving
+// exchanges plus 6 - log2(V) plain ones.  At the halving exchange with offset
+// o a lane keeps the half of its values selected by (lane & o) and adds its
+// partner's copy of that half.  Afterwards lane l holds the total of value
+// l >> (6 - log2 V).
+template <int V>
+__device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
+  static_assert(V >= 1 && V <= 64 && (V & (V - 1)) == 0, "V must be a power of two up to 64");
+  constexpr int LOG = __builtin_ctz(V);
+#pragma unroll
+  for (int s = 0; s < LOG; ++s) {
+    const int o = 32 >> s;
+    const int H = V >> (s + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = up ? v[i + H] : v[i];
+      const double give = up ? v[i] : v[i + H];
+      v[i] = keep + __shfl_xor(give, o, 64);
+    }
+  }
+  double t = v[0];
+#pragma unroll
+  for (int o = 32 >> LOG; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
 }  // namespace qoc
 
 namespace qoc {

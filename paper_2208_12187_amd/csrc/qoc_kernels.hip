@@ -170,35 +170,53 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
-template <typename T, int D, typename Ops>
+template <typename T, int D, typename Ops, int G>
 __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn) {
-  // Thread t owns the D/4 consecutive elements [t D/4, (t+1) D/4) of one row,
-  // read with 16-byte loads (coalesced across the workgroup) and written to
-  // LDS four columns at a time.
+  // The matrix is read as D^2/4 chunks of four consecutive row elements;
+  // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
+  // lanes of one 16-byte load read consecutive chunks.  Chunks are written to
+  // LDS four columns at a time.  The controls are read G at a time so that
+  // their load latencies overlap; indices past the last control are clamped
+  // to it and weighted by zero, which leaves every sum unchanged.
   using v4 = typename Prec<T>::v4;
-  constexpr int EPT = D / 4;
-  constexpr int NV = EPT / 4;
+  constexpr int NV = D / 16;
+  constexpr int NT = 4 * D;
   const T* H = reinterpret_cast<const T*>(P.Hint);
-  const int e0 = threadIdx.x * EPT;
+  const int e0 = 4 * threadIdx.x;
   v4 hr[NV], hi[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    hr[v] = Prec<T>::ld4(H + e0 + 4 * v);
-    hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * v);
+    hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
+    hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
   }
-  for (int j = 0; j < P.m; ++j) {
-    const T uj = (T)P.u[(size_t)j * P.N + k];
-    const T* Hj = H + (size_t)(j + 1) * 2 * D * D;
+  for (int j0 = 0; j0 < P.m; j0 += G) {
+    v4 ar[G][NV], ai[G][NV];
+    T uw[G];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      hr[v] += uj * Prec<T>::ld4(Hj + e0 + 4 * v);
-      hi[v] += uj * Prec<T>::ld4(Hj + D * D + e0 + 4 * v);
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = min(j0 + jj, P.m - 1);
+      uw[jj] = j0 + jj < P.m ? (T)P.u[(size_t)j * P.N + k] : (T)0;
+      const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ar[jj][v] = Prec<T>::ld4(Hj + 4 * NT * v);
+        ai[jj][v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+      }
     }
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        hr[v] += uw[jj] * ar[jj][v];
+        hi[v] += uw[jj] * ai[jj][v];
+      }
   }
   const T f = (T)(sgn * c);
-  const int row = e0 / D, col = e0 % D;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Ops::put4(lds, row, col + 4 * v, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
+  for (int v = 0; v < NV; ++v) {
+    const int e = e0 + 4 * NT * v;
+    Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
+  }
 }
 
 __device__ __forceinline__ void unpack_sq(int sq, int& s, int& q, int& qb) {
@@ -285,55 +303,132 @@ __device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel
   }
 }
 
-// Z = Z_k (panel): T_j = Tr(Z^dag Hc[j]) with FP64 accumulation and
-// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  Controls are taken in groups
-// of kEpiGroup: every wavefront reduces its partial sums of the group, one
-// barrier publishes them, and one thread per control finishes the sum over
-// wavefronts.  red: 2 x kEpiGroup x 2 x D/16 doubles of LDS (double-buffered
-// by group).
-constexpr int kEpiGroup = 16;
+// Gradient from Z = Z_k: T_j = Tr(Z^dag Hc[j]) with FP64 accumulation and
+// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  Controls are taken kEpiGroup
+// at a time: every lane forms its partial sums for the whole group (the
+// group's loads are independent, so their latencies overlap), one
+// multi-value wavefront reduction combines them, one barrier publishes the
+// per-wavefront totals and one thread per control adds those up.  Control
+// indices past the last one are clamped to it, so every load stays in bounds
+// and the surplus sums are discarded.  red: 2 x 2 kEpiGroup x (threads / 64)
+// doubles of LDS (double-buffered by group).
+constexpr int kEpiGroup = 4;
 
+template <int NWAVES>
+__device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j0, int grp, double (&v)[2 * kEpiGroup],
+                                                 const Lane& L, double* red) {
+  constexpr int V = 2 * kEpiGroup;
+  constexpr int SH = 6 - __builtin_ctz(V);
+  const int nj = min(kEpiGroup, P.m - j0);
+  const double t = wave_sum_many<V>(v, L.lane);
+  double* rg = red + (grp & 1) * V * NWAVES;
+  if ((L.lane & ((1 << SH) - 1)) == 0) rg[(L.lane >> SH) * NWAVES + L.w] = t;
+  __syncthreads();
+  if ((int)threadIdx.x < nj) {
+    const int jj = threadIdx.x;
+    double a = 0, b = 0;
+    for (int w = 0; w < NWAVES; ++w) {
+      a += rg[(2 * jj) * NWAVES + w];
+      b += rg[(2 * jj + 1) * NWAVES + w];
+    }
+    const double pref = 2.0 * P.dt / ((double)P.d * P.d);
+    P.grad[(size_t)(j0 + jj) * P.N + k] = pref * (P.g[0] * b - P.g[1] * a);
+  }
+}
+
+// D <= 64: Z goes through LDS (the caller's left-factor space, free once every
+// wavefront has finished its products), so that thread t owns the chunks of
+// four consecutive row elements t, t + 4D, t + 8D, ... and reads each
+// control's matching chunks with 16-byte loads, consecutive across lanes.
 template <typename T, int D>
 __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
-                                                  double* red) {
-  constexpr int NW = D / 16;
+                                                  void* lds, double* red) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int NV = D / 16;
+  constexpr int EPT = 4 * NV;
+  constexpr int NT = 4 * D;
+  constexpr int SD = Mat<T, D>::SD;
+  T* zl = static_cast<T*>(lds);
+  __syncthreads();  // every wavefront is done with the left factors
+  panel_to_lds(zl, Z, L);
+  __syncthreads();
+  const int e0 = 4 * threadIdx.x;
+  double zr[EPT], zi[EPT];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = e0 + 4 * NT * q;
+      const int off = lds_off<T, D>(e / D, e % D + i);
+      zr[4 * q + i] = (double)zl[off];
+      zi[4 * q + i] = (double)zl[D * SD + off];
+    }
+  // controls whose row segments are loaded together (register budget)
+  constexpr int LG = sizeof(T) == 4 ? kEpiGroup : 2;
   const T* H = reinterpret_cast<const T*>(P.Hint);
-  const double gr = P.g[0], gi = P.g[1];
-  const double pref = 2.0 * P.dt / ((double)P.d * P.d);
   for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
-    const int nj = min(kEpiGroup, P.m - j0);
-    double* rg = red + (grp & 1) * kEpiGroup * 2 * NW;
-    for (int jj = 0; jj < nj; ++jj) {
-      const T* Hr = H + (size_t)(j0 + jj + 1) * 2 * D * D;
+    double v[2 * kEpiGroup];
+#pragma unroll
+    for (int jb = 0; jb < kEpiGroup; jb += LG) {
+      v4 hr[LG][NV], hi[LG][NV];
+#pragma unroll
+      for (int jj = 0; jj < LG; ++jj) {
+        const int j = min(j0 + jb + jj, P.m - 1);
+        const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          hr[jj][q] = Prec<T>::ld4(Hj + 4 * NT * q);
+          hi[jj][q] = Prec<T>::ld4(Hj + D * D + 4 * NT * q);
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < LG; ++jj) {
+        double tr = 0, ti = 0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double a = zr[4 * q + i], b = zi[4 * q + i];
+            const double x = (double)hr[jj][q][i], y = (double)hi[jj][q][i];
+            tr += a * x + b * y;  // conj(z) h
+            ti += a * y - b * x;
+          }
+        v[2 * (jb + jj)] = tr;
+        v[2 * (jb + jj) + 1] = ti;
+      }
+    }
+    epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
+  }
+}
+
+// D = 128: Z stays in its register panels (one 16-column panel per
+// wavefront) and each lane reads the control elements at its panel positions.
+template <typename T, int D>
+__device__ __forceinline__ void gradient_epilogue_panel(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
+                                                        double* red) {
+  const T* H = reinterpret_cast<const T*>(P.Hint);
+  for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
+    double v[2 * kEpiGroup];
+#pragma unroll
+    for (int jj = 0; jj < kEpiGroup; ++jj) {
+      const int j = min(j0 + jj, P.m - 1);
+      const T* Hr = H + (size_t)(j + 1) * 2 * D * D;
       const T* Hi = Hr + D * D;
       double tr = 0, ti = 0;
 #pragma unroll
       for (int rb = 0; rb < D / 16; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
-          double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
-          double hr = (double)Hr[e], hi = (double)Hi[e];
+          const int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
+          const double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
+          const double hr = (double)Hr[e], hi = (double)Hi[e];
           tr += zr * hr + zi * hi;  // conj(z) h
           ti += zr * hi - zi * hr;
         }
-      tr = wave_sum(tr);
-      ti = wave_sum(ti);
-      if (L.lane == 0) {
-        rg[(jj * NW + L.w) * 2] = tr;
-        rg[(jj * NW + L.w) * 2 + 1] = ti;
-      }
+      v[2 * jj] = tr;
+      v[2 * jj + 1] = ti;
     }
-    __syncthreads();
-    if ((int)threadIdx.x < nj) {
-      const int jj = threadIdx.x;
-      double a = 0, b = 0;
-      for (int w = 0; w < NW; ++w) {
-        a += rg[(jj * NW + w) * 2];
-        b += rg[(jj * NW + w) * 2 + 1];
-      }
-      P.grad[(size_t)(j0 + jj) * P.N + k] = pref * (gr * b - gi * a);
-    }
+    epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
   }
 }
 
@@ -353,7 +448,7 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
-  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0);
+  assemble<T, D, Ops, 1>(lds, P, k, ldexp(P.dt, -s), 1.0);
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
@@ -624,7 +719,7 @@ void k_adjoint(Work W) {
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
   Ops::store(lds[1], R2, L);
-  assemble<T, D, Ops>(lds[0], P, k, ldexp(P.dt, -s), -1.0);
+  assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0);
   __syncthreads();
   const void* X = lds[0];
   const void* E = lds[1];
@@ -666,7 +761,7 @@ void k_adjoint(Work W) {
   }
 
   // 5. inner products with the controls (FP64), then the gradient
-  gradient_epilogue<T, D>(P, k, A2, L, red);
+  gradient_epilogue<T, D>(P, k, A2, L, lds[0], red);
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
   }
@@ -1067,7 +1162,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
         panel_load(acc, S0, L);
       }
     }
-    gradient_epilogue<T, 128>(P, k, acc, L, red);
+    gradient_epilogue_panel<T, 128>(P, k, acc, L, red);
     __syncthreads();
   }
 }
