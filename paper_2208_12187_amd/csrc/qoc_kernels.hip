@@ -171,13 +171,14 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
 template <typename T, int D, typename Ops, int G>
-__device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn) {
+__device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk) {
   // The matrix is read as D^2/4 chunks of four consecutive row elements;
   // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
   // lanes of one 16-byte load read consecutive chunks.  Chunks are written to
   // LDS four columns at a time.  The controls are read G at a time so that
   // their load latencies overlap; indices past the last control are clamped
-  // to it and weighted by zero, which leaves every sum unchanged.
+  // to it and weighted by zero, which leaves every sum unchanged.  When hk is
+  // not null, H_k itself is also written there (planar, row-major).
   using v4 = typename Prec<T>::v4;
   constexpr int NV = D / 16;
   constexpr int NT = 4 * D;
@@ -216,6 +217,32 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
   for (int v = 0; v < NV; ++v) {
     const int e = e0 + 4 * NT * v;
     Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
+    if (hk) {
+      Prec<T>::st4(hk + e, hr[v]);
+      Prec<T>::st4(hk + D * D + e, hi[v]);
+    }
+  }
+}
+
+// The slice's H_k as stored by k_expm, scaled and written to LDS exactly as
+// assemble() writes it (the same values bit for bit).
+template <typename T, int D, typename Ops>
+__device__ __forceinline__ void load_hamiltonian(void* lds, const T* hk, double c, double sgn) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int NV = D / 16;
+  constexpr int NT = 4 * D;
+  const int e0 = 4 * threadIdx.x;
+  v4 hr[NV], hi[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    hr[v] = Prec<T>::ld4(hk + e0 + 4 * NT * v);
+    hi[v] = Prec<T>::ld4(hk + D * D + e0 + 4 * NT * v);
+  }
+  const T f = (T)(sgn * c);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int e = e0 + 4 * NT * v;
+    Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);
   }
 }
 
@@ -448,7 +475,8 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
-  assemble<T, D, Ops, 1>(lds, P, k, ldexp(P.dt, -s), 1.0);
+  T* hk = (P.hk && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
+  assemble<T, D, Ops, 1>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
@@ -719,7 +747,8 @@ void k_adjoint(Work W) {
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
   Ops::store(lds[1], R2, L);
-  assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0);
+  if (P.hk) load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
+  else assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
   __syncthreads();
   const void* X = lds[0];
   const void* E = lds[1];

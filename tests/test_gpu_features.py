@@ -10,8 +10,9 @@ from workloads import make_batch, make_config
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("cfg,N,prec", [(3, 300, "fp32"), (4, 60, "fp64"), (2, 101, "fp64")])
-def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec):
+@pytest.mark.parametrize("cfg,N,prec,seg", [(3, 300, "fp32", 1), (3, 300, "fp32", 2), (4, 60, "fp64", 1),
+                                            (2, 101, "fp64", 1)])
+def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec, seg):
     import torch
     from paper_2208_12187_amd import qoc
 
@@ -23,9 +24,12 @@ def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec):
     mat = 2 * D * D * (8 if prec == "fp64" else 4)
     L = int(np.ceil(np.sqrt(N)))
     P = -(-N // L)
-    small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=2 * (5 * P + 3 * L + 1) * mat)  # one-chunk segments
+    per_slice = 3 if D == 128 else 4  # stored propagators, plus the slice Hamiltonians at D <= 64
+    budget = 2 * (5 * P + seg * per_slice * L + 1) * mat  # segments of `seg` chunks
+    small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=budget)
     assert small.ws_bytes < full.ws_bytes
-    print(f"[features] checkpoint cfg{cfg} N={N} {prec}: {full.ws_bytes} -> {small.ws_bytes} bytes", flush=True)
+    print(f"[features] checkpoint cfg{cfg} N={N} {prec} seg={seg}: {full.ws_bytes} -> {small.ws_bytes} bytes",
+          flush=True)
     F1, g1 = full.gradient(b)
     F2, g2 = small.gradient(b)
     torch.cuda.synchronize()
