@@ -28,19 +28,29 @@ CFG = 3  # 6-qubit Ising chain, d = 64
 WORKLOADS = {2: "4-qubit Heisenberg chain", 3: "6-qubit Ising chain", 4: "7-qubit Heisenberg chain"}
 
 
-def slice_flops(plan: np.ndarray, d: int, m: int) -> dict:
-    """Algorithmic real flops per stage for slices with plan rows (s, q, qb).
+def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
+    """MFMA flops per stage of the implemented algorithm for slices with plan
+    rows (s, q, qb), and the adjoint's count in the conventional 8 d^3 per
+    complex product ("adjoint_8d3").
 
-    A complex d x d product is 8 d^3 flops.  expm: q - 1 + s products and the
-    assembly (4 m d^2); scans: one product per slice in each direction;
-    adjoint: three products per block Horner step or squaring,
-    3 (qb - 1 + s), plus assembly and the m inner products (12 m d^2)."""
+    Complex d x d products per slice: expm q - 1 + s; scans one per
+    direction; adjoint 3 (qb + s) - 2 (two for W, three per block Horner
+    step or squaring, less the top-left blocks the last step does not need).
+    A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
+    the three-product (Gauss) form, which the FP32/FP64 adjoint and the FP32
+    expm use at d >= 32.  The split-BF16 path issues three BF16 products per
+    real one, 24 d^3 BF16 flops per complex product.  Assembly and the
+    gradient inner products run on the vector ALU and are not counted."""
     s, q, qb = plan[:, 0].astype(np.float64), plan[:, 1].astype(np.float64), plan[:, 2].astype(np.float64)
-    G = 8.0 * d ** 3
-    expm = G * (q - 1 + s) + 4.0 * m * d * d
-    scan = np.full_like(s, 2 * G)
-    adj = G * 3 * (qb - 1 + s) + 12.0 * m * d * d
-    return {"expm": float(expm.sum()), "scan": float(scan.sum()), "adjoint": float(adj.sum())}
+    G4, G3 = 8.0 * d ** 3, 6.0 * d ** 3
+    three = prec in ("fp32", "fp64") and 32 <= d <= 64
+    if prec == "bf16x3":
+        G4 = G3 = 24.0 * d ** 3
+    g_adj = G3 if three else G4
+    g_expm = G3 if (three and prec == "fp32") else G4
+    n_adj = 3 * (qb + s) - 2
+    return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * G4 * len(s)),
+            "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
 
 
 def time_runner(qoc, torch, runner, batch, steps, warmup):
@@ -147,7 +157,7 @@ def main():
     batch = qoc.Batch.from_problems(problems)
     plans = {pr: np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, pr, True) for p in problems])
              for pr in ("fp32", "fp64", "bf16x3")}
-    flops = {pr: slice_flops(plans[pr], d, m) for pr in plans}
+    flops = {pr: slice_flops(plans[pr], d, m, pr) for pr in plans}
 
     def leg(prec, steps, bsz=B, bat=batch):
         r = qoc.Runner(bsz, d, m, N, prec)
@@ -170,8 +180,13 @@ def main():
                                                           and B == 32) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None if traffic is None else round(traffic),
-                "kernel": "k_adjoint", "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4)}
-    total_flops = sum(flops[args.precision].values())
+                "kernel": "k_adjoint", "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4),
+                "cgemm_8d3_tflops": round(flops[args.precision]["adjoint_8d3"] / adj_avg_s / 1e12, 2)}
+
+    def path_flops(pr):
+        return sum(v for k, v in flops[pr].items() if k != "adjoint_8d3")
+
+    total_flops = path_flops(args.precision)
     stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in head["stages"].items() if v[1]}
 
     extra = {}
@@ -180,7 +195,7 @@ def main():
         v64 = B * N / (f64["ms_per_step"] / 1e3)
         extra["fp64"] = {"value": round(v64, 1), "ms_per_step": round(f64["ms_per_step"], 3),
                          "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in f64["stages"].items() if v[1]},
-                         "path_tflops": round(sum(flops["fp64"].values()) / (f64["ms_per_step"] / 1e3) / 1e12, 2)}
+                         "path_tflops": round(path_flops("fp64") / (f64["ms_per_step"] / 1e3) / 1e12, 2)}
         extra["speedup_vs_fp64"] = round(value / v64, 3)
         extra["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(head["F"] - f64["F"])))
     if not args.no_bf16 and args.precision != "bf16x3" and 16 < d <= 64:
@@ -189,7 +204,9 @@ def main():
         adj3_ms, adj3_n = b3["stages"]["adjoint"]
         extra["bf16x3"] = {"value": round(v3, 1), "ms_per_step": round(b3["ms_per_step"], 3),
                            "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in b3["stages"].items() if v[1]},
-                           "adjoint_fp32_equiv_tflops": round(flops["bf16x3"]["adjoint"] / (adj3_ms / max(adj3_n, 1) / 1e3) / 1e12, 2),
+                           "adjoint_fp32_equiv_tflops": round(flops["bf16x3"]["adjoint_8d3"] / (adj3_ms / max(adj3_n, 1) / 1e3) / 1e12, 2),
+                           "adjoint_bf16_mfma_frac": round(flops["bf16x3"]["adjoint"] / (adj3_ms / max(adj3_n, 1) / 1e3)
+                                                           / 1e12 / PEAK_TFLOPS["bf16x3"], 4),
                            "max_abs_dF_vs_fp32": float(np.max(np.abs(b3["F"] - head["F"]))),
                            "grad_err_vs_fp32": float((b3["grad"] - head["grad"]).abs().max().item()
                                                      / head["grad"].abs().max().item())}
@@ -216,7 +233,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{WORKLOADS[args.config]} GRAPE fwd+grad, d={d}, m={m}, N={N}, "
                                f"dt={problems[0].dt}, batch of {B} seeded problems",

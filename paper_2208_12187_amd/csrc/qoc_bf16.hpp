@@ -179,6 +179,11 @@ struct Bf3Ops {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
 
+  __device__ static __forceinline__ void gemm3(Panel<float, D>& acc, const void* lds, const Panel<float, D>& P,
+                                               const Lane& L, bool zero_acc) {
+    gemm(acc, lds, P, L, zero_acc);
+  }
+
   // acc (+)= A P with A the LDS matrix: per K step t the panel's 8 values are
   // split once; per row block 4 x 16-byte reads and 12 MFMAs.
   __device__ static __forceinline__ void gemm(Panel<float, D>& acc, const void* lds, const Panel<float, D>& P,

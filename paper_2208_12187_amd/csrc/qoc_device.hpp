@@ -270,6 +270,67 @@ __device__ __forceinline__ void cgemm(Panel<T, D>& acc, const T* A, const Panel<
   }
 }
 
+// The same product with three real products per complex one (Gauss; the "3M" method):
+// T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi), Re = T1 - T2 and
+// Im = T3 - T1 - T2.  T1 accumulates in acc.re and T3 in acc.im, which
+// starts at acc.im + acc.re so that the final Im = T3 - T1 - T2 keeps the
+// incoming acc.im; its error bound is a small multiple of that of the
+// four-product form (Higham, Accuracy and Stability of Numerical Algorithms,
+// 2nd ed., sec. 23.2.4).
+//
+// It needs two more register sets (the B sums and T2) than cgemm, so kernels
+// use it where their occupancy allows.
+template <typename T, int D>
+__device__ __forceinline__ void cgemm3m(Panel<T, D>& acc, const T* A, const Panel<T, D>& P, const Lane& L,
+                                      bool zero_acc) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int RB = D / 16;
+  constexpr int SD = Mat<T, D>::SD;
+  constexpr int STEPS = RB * RB;
+  const T* Ai = A + D * SD;
+  const int base = L.c16 * SD + 4 * L.g;
+  __builtin_amdgcn_sched_barrier(0);
+  v4 bs[RB], t2[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    bs[rb] = P.re[rb] + P.im[rb];
+    t2[rb] = (v4){0, 0, 0, 0};
+    if (zero_acc) {
+      acc.re[rb] = (v4){0, 0, 0, 0};
+      acc.im[rb] = (v4){0, 0, 0, 0};
+    } else {
+      acc.im[rb] += acc.re[rb];
+    }
+  }
+  v4 ar[2], ai[2];
+  ar[0] = Prec<T>::ld4(A + base);
+  ai[0] = Prec<T>::ld4(Ai + base);
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st) {
+    const int kb = st / RB, mb = st % RB;
+    const int cur = st & 1;
+    if (st + 1 < STEPS) {
+      const int kn = (st + 1) / RB, mn = (st + 1) % RB;
+      const int off = base + 16 * mn * SD + 16 * kn;
+      ar[cur ^ 1] = Prec<T>::ld4(A + off);
+      ai[cur ^ 1] = Prec<T>::ld4(Ai + off);
+    }
+    const v4 as = ar[cur] + ai[cur];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc.re[mb] = Prec<T>::mfma(ar[cur][r], P.re[kb][r], acc.re[mb]);
+      t2[mb] = Prec<T>::mfma(ai[cur][r], P.im[kb][r], t2[mb]);
+      acc.im[mb] = Prec<T>::mfma(as[r], bs[kb][r], acc.im[mb]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    acc.im[rb] = acc.im[rb] - acc.re[rb] - t2[rb];
+    acc.re[rb] = acc.re[rb] - t2[rb];
+  }
+}
+
 // ---------------------------------------------------------------- stored (PF) matrices
 
 template <typename T, int D>
@@ -404,6 +465,13 @@ struct StdOps {
   __device__ static __forceinline__ void gemm(Panel<T, D>& acc, const void* lds, const Panel<T, D>& P, const Lane& L,
                                               bool zero_acc) {
     cgemm(acc, static_cast<const T*>(lds), P, L, zero_acc);
+  }
+  // The same product in the three-product form where it pays (D >= 32; at
+  // D = 16 the extra registers cost more occupancy than the saved MFMAs).
+  __device__ static __forceinline__ void gemm3(Panel<T, D>& acc, const void* lds, const Panel<T, D>& P,
+                                               const Lane& L, bool zero_acc) {
+    if constexpr (D >= 32) cgemm3m(acc, static_cast<const T*>(lds), P, L, zero_acc);
+    else cgemm(acc, static_cast<const T*>(lds), P, L, zero_acc);
   }
 };
 

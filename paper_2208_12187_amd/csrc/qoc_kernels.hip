@@ -464,6 +464,16 @@ __device__ __forceinline__ void gradient_epilogue_panel(const ProbDesc& P, int k
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
 // Horner in delta form: R_q = I + X/q, R_i = I + X R_{i+1} / i, Delta = X R_2
 // (X = A_k / 2^s), then s squarings Delta <- 2 Delta + Delta^2.
+// The expm kernel takes the three-product form in FP32, where the extra
+// registers leave its occupancy unchanged, and not in FP64, where they would
+// halve it at D = 64.
+template <typename T, int D, typename Ops>
+__device__ __forceinline__ void expm_gemm(Panel<T, D>& acc, const void* lds, const Panel<T, D>& P, const Lane& L,
+                                          bool zero_acc) {
+  if constexpr (sizeof(T) == 4) Ops::gemm3(acc, lds, P, L, zero_acc);
+  else Ops::gemm(acc, lds, P, L, zero_acc);
+}
+
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   __shared__ __align__(16) unsigned char lds[Ops::BYTES];
@@ -484,19 +494,19 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
     panel_scale(R, (T)(1.0 / q));
     panel_add_identity(R, L, (T)1);
     for (int i = q - 1; i >= 2; --i) {
-      Ops::gemm(acc, lds, R, L, true);
+      expm_gemm<T, D, Ops>(acc, lds, R, L, true);
       R = acc;
       panel_scale(R, (T)(1.0 / i));
       panel_add_identity(R, L, (T)1);
     }
-    Ops::gemm(acc, lds, R, L, true);
+    expm_gemm<T, D, Ops>(acc, lds, R, L, true);
     R = acc;
   }
   for (int j = 0; j < s; ++j) {
     __syncthreads();
     Ops::store(lds, R, L);
     __syncthreads();
-    Ops::gemm(acc, lds, R, L, true);
+    expm_gemm<T, D, Ops>(acc, lds, R, L, true);
     panel_axpby(R, (T)1, acc, (T)2);
   }
   panel_store(pf_mat<T, D>(P.delta, k - W.rg.kbase), R, L);
@@ -736,11 +746,11 @@ void k_adjoint(Work W) {
   panel_load(R2, pf_mat<T, D>(P.bloc, k - W.rg.kbase), L);
   __syncthreads();
   Ops::load_ct(A2, lds[1], L);
-  Ops::gemm(A1, lds[0], A2, L, true);
+  Ops::gemm3(A1, lds[0], A2, L, true);
   __syncthreads();
   Ops::store(lds[0], R2, L);
   __syncthreads();
-  Ops::gemm(R2, lds[0], A1, L, true);  // R2 = W
+  Ops::gemm3(R2, lds[0], A1, L, true);  // R2 = W
   __syncthreads();
 
   // 2. E = W / 2^s, X = A^dag / 2^s
@@ -759,9 +769,9 @@ void k_adjoint(Work W) {
   panel_add_identity(R1, L, (T)1);
   panel_scale(R2, (T)(1.0 / qb));
   for (int i = qb - 1; i >= 2; --i) {
-    Ops::gemm(A2, X, R2, L, true);
-    Ops::gemm(A2, E, R1, L, false);
-    Ops::gemm(A1, X, R1, L, true);
+    Ops::gemm3(A2, X, R2, L, true);
+    Ops::gemm3(A2, E, R1, L, false);
+    Ops::gemm3(A1, X, R1, L, true);
     const T inv = (T)(1.0 / i);
     R1 = A1;
     panel_scale(R1, inv);
@@ -769,9 +779,9 @@ void k_adjoint(Work W) {
     R2 = A2;
     panel_scale(R2, inv);
   }
-  Ops::gemm(A2, X, R2, L, true);
-  Ops::gemm(A2, E, R1, L, false);  // A2 = Q (top-right of the delta block)
-  if (s > 0) Ops::gemm(A1, X, R1, L, true);  // A1 = D1 (top-left)
+  Ops::gemm3(A2, X, R2, L, true);
+  Ops::gemm3(A2, E, R1, L, false);  // A2 = Q (top-right of the delta block)
+  if (s > 0) Ops::gemm3(A1, X, R1, L, true);  // A1 = D1 (top-left)
 
   // 4. squarings
   for (int j = 0; j < s; ++j) {
@@ -779,11 +789,11 @@ void k_adjoint(Work W) {
     Ops::store(lds[0], A1, L);
     Ops::store(lds[1], A2, L);
     __syncthreads();
-    Ops::gemm(R2, lds[0], A2, L, true);   // D1 Q
-    Ops::gemm(R2, lds[1], A1, L, false);  // + Q D1
+    Ops::gemm3(R2, lds[0], A2, L, true);   // D1 Q
+    Ops::gemm3(R2, lds[1], A1, L, false);  // + Q D1
     panel_axpby(R2, (T)2, A2, (T)1);  // R2 = 2Q + D1 Q + Q D1
     if (j + 1 < s) {
-      Ops::gemm(R1, lds[0], A1, L, true);
+      Ops::gemm3(R1, lds[0], A1, L, true);
       panel_axpby(A1, (T)1, R1, (T)2);
     }
     A2 = R2;

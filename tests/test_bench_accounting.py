@@ -1,0 +1,43 @@
+"""Host-side checks of the bench's flop accounting: the per-slice product
+counts follow the kernels' Horner and squaring loops, and the three-product
+form is counted only where the kernels use it."""
+import numpy as np
+
+import bench
+
+
+def _products_adjoint(s, qb):
+    # W = bloc (mc xprev^dag): two products; block Horner from degree qb:
+    # three products per step, the last step without the top-left block
+    # unless squarings follow; each squaring three, the last without the
+    # top-left block.
+    n = 2 + 3 * (qb - 2) + 2 + (1 if s > 0 else 0)
+    for j in range(s):
+        n += 2 + (1 if j + 1 < s else 0)
+    return n
+
+
+def test_adjoint_product_count_matches_the_loop_structure():
+    for s in range(0, 4):
+        for qb in range(2, 10):
+            plan = np.array([[s, max(qb - 1, 1), qb]], dtype=np.int32)
+            f = bench.slice_flops(plan, 64, 12, "fp32")
+            assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, qb)
+
+
+def test_three_product_form_is_counted_where_used():
+    plan = np.array([[0, 3, 4], [1, 3, 4]], dtype=np.int32)
+    d = 64
+    f32 = bench.slice_flops(plan, d, 12, "fp32")
+    f64 = bench.slice_flops(plan, d, 12, "fp64")
+    b16 = bench.slice_flops(plan, d, 12, "bf16x3")
+    n_adj = 10 + 13
+    assert f32["adjoint"] == 6.0 * d ** 3 * n_adj and f64["adjoint"] == 6.0 * d ** 3 * n_adj
+    assert b16["adjoint"] == 24.0 * d ** 3 * n_adj and b16["adjoint_8d3"] == 8.0 * d ** 3 * n_adj
+    # expm: q - 1 + s products, three-product form in FP32 only
+    assert f32["expm"] == 6.0 * d ** 3 * (2 + 3) and f64["expm"] == 8.0 * d ** 3 * (2 + 3)
+    assert f32["scan"] == 2 * 8.0 * d ** 3 * 2
+    # d = 16 and d = 128 use the four-product form everywhere
+    for dd in (16, 128):
+        f = bench.slice_flops(plan, dd, 8, "fp32")
+        assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * dd ** 3 * 5
