@@ -217,6 +217,16 @@ def main():
         one = leg(args.precision, args.steps, 1, b1)
         extra["batch1"] = {"value": round(N / (one["ms_per_step"] / 1e3), 1),
                            "ms_per_step": round(one["ms_per_step"], 3)}
+        # the host-pointer entry point on the same problem: device allocation,
+        # host-to-device copies, the path and the copy back, per call
+        p0 = problems[0]
+        qoc.gradient(p0.H0, p0.Hc, p0.u, p0.dt, p0.V, args.precision)
+        t0 = time.perf_counter()
+        calls = 5
+        for _ in range(calls):
+            qoc.gradient(p0.H0, p0.Hc, p0.u, p0.dt, p0.V, args.precision)
+        host_ms = (time.perf_counter() - t0) / calls * 1e3
+        extra["host_api_pcie_inclusive"] = {"value": round(N / (host_ms / 1e3), 1), "ms_per_call": round(host_ms, 3)}
 
     cpu = None
     if not args.no_cpu:
