@@ -428,37 +428,6 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
   }
 }
 
-// D = 128: Z stays in its register panels (one 16-column panel per
-// wavefront) and each lane reads the control elements at its panel positions.
-template <typename T, int D>
-__device__ __forceinline__ void gradient_epilogue_panel(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
-                                                        double* red) {
-  const T* H = reinterpret_cast<const T*>(P.Hint);
-  for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
-    double v[2 * kEpiGroup];
-#pragma unroll
-    for (int jj = 0; jj < kEpiGroup; ++jj) {
-      const int j = min(j0 + jj, P.m - 1);
-      const T* Hr = H + (size_t)(j + 1) * 2 * D * D;
-      const T* Hi = Hr + D * D;
-      double tr = 0, ti = 0;
-#pragma unroll
-      for (int rb = 0; rb < D / 16; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = (16 * rb + Prec<T>::rowmap(r, L.g)) * D + 16 * L.w + L.c16;
-          const double zr = (double)Z.re[rb][r], zi = (double)Z.im[rb][r];
-          const double hr = (double)Hr[e], hi = (double)Hi[e];
-          tr += zr * hr + zi * hi;  // conj(z) h
-          ti += zr * hi - zi * hr;
-        }
-      v[2 * jj] = tr;
-      v[2 * jj + 1] = ti;
-    }
-    epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
-  }
-}
-
 // ---------------------------------------------------------------- slice propagators
 
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
@@ -972,28 +941,184 @@ __device__ __forceinline__ void transpose128(T* out, T* lds, const T* M, const L
   }
 }
 
-// out (PF) <- sgn * (-i) * c * H_k, all 512 threads, coalesced reads of the
-// planar control matrices.
+// Write the chunk (row, col..col+3) of sgn * (-i) * c * (hr + i hi) into the
+// PF matrix out.
 template <typename T>
-__device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, double c, double sgn) {
+__device__ __forceinline__ void put4_pf128(T* out, int e, T f, const typename Prec<T>::v4& hr,
+                                           const typename Prec<T>::v4& hi) {
   constexpr int D = 128;
+  const int row = e / D, col = e % D;
+  const int rb = row >> 4, rr = row & 15;
+  int r, g;
+  if (sizeof(T) == 4) { g = rr >> 2; r = rr & 3; } else { r = rr >> 2; g = rr & 3; }
+  const int reg = 4 * rb + r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int w = (col + i) >> 4, lane = 16 * g + ((col + i) & 15);
+    out[pf_index<T, D>(w, 0, reg, lane)] = f * hi[i];
+    out[pf_index<T, D>(w, 1, reg, lane)] = -f * hr[i];
+  }
+}
+
+// out (PF) <- sgn * (-i) * c * H_k with H_k = H0 + sum_j u_jk Hc[j]; when hk
+// is not null, H_k itself is also written there (planar, row-major).  The
+// matrix is read as chunks of four consecutive row elements, chunk t + 512 i
+// by thread t, so that every 16-byte load is consecutive across lanes and a
+// control's loads are all in flight together (FP64: half the chunks per pass).
+template <typename T>
+__device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, double c, double sgn, T* hk) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int D = 128, NT = 512;
+  constexpr int PASSES = sizeof(T) == 4 ? 1 : 2;
+  constexpr int NV = D * D / 4 / NT / PASSES;
   const T* H = reinterpret_cast<const T*>(P.Hint);
   const T f = (T)(sgn * c);
-  for (int e = threadIdx.x; e < D * D; e += 512) {
-    T hr = H[e], hi = H[D * D + e];
+#pragma unroll
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int e0 = 4 * (threadIdx.x + pass * NV * NT);
+    v4 hr[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
+      hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
+    }
     for (int j = 0; j < P.m; ++j) {
       const T uj = (T)P.u[(size_t)j * P.N + k];
-      const T* Hj = H + (size_t)(j + 1) * 2 * D * D;
-      hr += uj * Hj[e];
-      hi += uj * Hj[D * D + e];
+      const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+      v4 ar[NV], ai[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ar[v] = Prec<T>::ld4(Hj + 4 * NT * v);
+        ai[v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        hr[v] += uj * ar[v];
+        hi[v] += uj * ai[v];
+      }
     }
-    const int row = e / D, col = e % D;
-    const int w = col >> 4, c16 = col & 15, rb = row >> 4, rr = row & 15;
-    int r, g;
-    if (sizeof(T) == 4) { g = rr >> 2; r = rr & 3; } else { r = rr >> 2; g = rr & 3; }
-    const int lane = 16 * g + c16, reg = 4 * rb + r;
-    out[pf_index<T, D>(w, 0, reg, lane)] = f * hi;
-    out[pf_index<T, D>(w, 1, reg, lane)] = -f * hr;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int e = e0 + 4 * NT * v;
+      if (hk) {
+        Prec<T>::st4(hk + e, hr[v]);
+        Prec<T>::st4(hk + D * D + e, hi[v]);
+      }
+      put4_pf128<T>(out, e, f, hr[v], hi[v]);
+    }
+  }
+}
+
+// out (PF) <- sgn * (-i) * c * H_k from the planar H_k that k_expm128 stored.
+template <typename T>
+__device__ __forceinline__ void load_hamiltonian128(T* out, const T* hk, double c, double sgn) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int D = 128, NT = 512;
+  constexpr int PASSES = sizeof(T) == 4 ? 1 : 2;
+  constexpr int NV = D * D / 4 / NT / PASSES;
+  const T f = (T)(sgn * c);
+#pragma unroll
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int e0 = 4 * (threadIdx.x + pass * NV * NT);
+    v4 hr[NV], hi[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      hr[v] = Prec<T>::ld4(hk + e0 + 4 * NT * v);
+      hi[v] = Prec<T>::ld4(hk + D * D + e0 + 4 * NT * v);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) put4_pf128<T>(out, e0 + 4 * NT * v, f, hr[v], hi[v]);
+  }
+}
+
+// The gradient epilogue at D = 128 (512 threads), as gradient_epilogue: Z goes
+// through LDS so that thread t owns the chunks of four consecutive row
+// elements t + 512 i and reads each control's chunks with 16-byte loads,
+// consecutive across lanes.  The chunks are taken in two passes over the row
+// halves (registers); FP32 stages all of Z once, FP64 stages the half of each
+// pass (one FP64 matrix does not fit in LDS).  Z is read from the PF matrix
+// Zpf, in which every wavefront has stored its own panel (so the staging
+// needs no barrier before its reads and holds no panel in registers).
+template <typename T>
+__device__ __forceinline__ void gradient_epilogue128(const ProbDesc& P, int k, const T* Zpf, const Lane& L,
+                                                     T* lds, double* red) {
+  using v4 = typename Prec<T>::v4;
+  constexpr int D = 128, NT = 512, NV = 4;
+  constexpr bool RESTAGE = sizeof(T) == 8;
+  constexpr int ROWS = RESTAGE ? 64 : 128;  // rows staged at once
+  constexpr int SD = D + Prec<T>::PAD;
+  static_assert(2 * ROWS * SD <= K128<T>::LDS_ELEMS, "LDS too small");
+  constexpr int LG = sizeof(T) == 4 ? 2 : 1;  // controls loaded together
+  T* lim = lds + ROWS * SD;
+  // Stage row blocks [rb0, rb0 + ROWS / 16) of Z, at local rows from 0.
+  auto stage = [&](int rb0) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ROWS / 16; ++i) {
+      v4 re, im;
+      pf_rb_load<T>(re, im, Zpf, L.w, rb0 + i, L.lane);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int off = (16 * i + Prec<T>::rowmap(r, L.g)) * SD + 16 * L.w + Prec<T>::perm(L.c16);
+        lds[off] = re[r];
+        lim[off] = im[r];
+      }
+    }
+    __syncthreads();
+  };
+  if (!RESTAGE) stage(0);
+  const T* H = reinterpret_cast<const T*>(P.Hint);
+  for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
+    double v[2 * kEpiGroup];
+#pragma unroll
+    for (int i = 0; i < 2 * kEpiGroup; ++i) v[i] = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (RESTAGE) stage(4 * h);
+      const int e0 = 4 * (threadIdx.x + h * NV * NT);
+      const int row0 = RESTAGE ? 64 * h : 0;
+      double zr[4 * NV], zi[4 * NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = e0 + 4 * NT * q;
+          const int col = e % D + i;
+          const int off = (e / D - row0) * SD + (col & ~15) + Prec<T>::perm(col & 15);
+          zr[4 * q + i] = (double)lds[off];
+          zi[4 * q + i] = (double)lim[off];
+        }
+#pragma unroll
+      for (int jb = 0; jb < kEpiGroup; jb += LG) {
+        v4 hr[LG][NV], hi[LG][NV];
+#pragma unroll
+        for (int jj = 0; jj < LG; ++jj) {
+          const int j = min(j0 + jb + jj, P.m - 1);
+          const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            hr[jj][q] = Prec<T>::ld4(Hj + 4 * NT * q);
+            hi[jj][q] = Prec<T>::ld4(Hj + D * D + 4 * NT * q);
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < LG; ++jj) {
+          double tr = 0, ti = 0;
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double a = zr[4 * q + i], b = zi[4 * q + i];
+              const double x = (double)hr[jj][q][i], y = (double)hi[jj][q][i];
+              tr += a * x + b * y;  // conj(z) h
+              ti += a * y - b * x;
+            }
+          v[2 * (jb + jj)] += tr;
+          v[2 * (jb + jj) + 1] += ti;
+        }
+      }
+    }
+    epilogue_publish<8>(P, k, j0, grp, v, L, red);
   }
 }
 
@@ -1016,7 +1141,8 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     __syncthreads();
-    assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0);
+    T* hk = (P.hk && (P.flags & RUN_GRAD)) ? pf_mat<T, 128>(P.hk, k - W.rg.kbase) : nullptr;
+    assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0, hk);
     __syncthreads();
     Panel<T, 128> acc;
     panel_load(acc, SX, L);
@@ -1162,7 +1288,8 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     panel_store(SR2, acc, L);
     // X = A^dag / 2^s, R1 = I + X / qb
     __syncthreads();
-    assemble128<T>(SX, P, k, ldexp(P.dt, -s), -1.0);
+    if (P.hk) load_hamiltonian128<T>(SX, pf_mat<T, 128>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
+    else assemble128<T>(SX, P, k, ldexp(P.dt, -s), -1.0, nullptr);
     __syncthreads();
     panel_load(acc, SX, L);
     panel_scale(acc, (T)(1.0 / qb));
@@ -1201,7 +1328,8 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
         panel_load(acc, S0, L);
       }
     }
-    gradient_epilogue_panel<T, 128>(P, k, acc, L, red);
+    panel_store(S0, acc, L);  // Z (own panel)
+    gradient_epilogue128<T>(P, k, S0, L, lds, red);
     __syncthreads();
   }
 }
