@@ -839,31 +839,41 @@ __device__ __forceinline__ void stage128(T* lds, const T* M, int h, const Lane& 
   using K = K128<T>;
   using v4 = typename Prec<T>::v4;
   T* lim = lds + K::D * K::SD;
+  // Row blocks are loaded NB at a time, all NB loads in flight before the
+  // LDS writes, so that the staging waits for RB / NB global round trips.
+  constexpr int NB = sizeof(T) == 4 ? 4 : 2;
   if constexpr (!CT) {
     if (L.w / K::WPH != h) return;
     const int lw = L.w - h * K::WPH;
 #pragma unroll
-    for (int rb = 0; rb < K::RB; ++rb) {
-      v4 re, im;
-      pf_rb_load<T>(re, im, M, L.w, rb, L.lane);
+    for (int b0 = 0; b0 < K::RB; b0 += NB) {
+      v4 re[NB], im[NB];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int off = (16 * rb + Prec<T>::rowmap(r, L.g)) * K::SD + 16 * lw + Prec<T>::perm(L.c16);
-        lds[off] = re[r];
-        lim[off] = im[r];
-      }
+      for (int i = 0; i < NB; ++i) pf_rb_load<T>(re[i], im[i], M, L.w, b0 + i, L.lane);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int off = (16 * (b0 + i) + Prec<T>::rowmap(r, L.g)) * K::SD + 16 * lw + Prec<T>::perm(L.c16);
+          lds[off] = re[i][r];
+          lim[off] = im[i][r];
+        }
       __builtin_amdgcn_sched_barrier(0);
     }
   } else {
     // M^dag[16w + c16][16 rb + rowmap(r, g)] = conj(M[16 rb + rowmap(r, g)][16w + c16])
+    constexpr int RL = K::RB / K::HALVES;
 #pragma unroll
-    for (int rl = 0; rl < K::RB / K::HALVES; ++rl) {
-      const int rb = h * (K::RB / K::HALVES) + rl;
-      v4 re, im;
-      pf_rb_load<T>(re, im, M, L.w, rb, L.lane);
-      int off = (16 * L.w + L.c16) * K::SD + 16 * rl + 4 * L.g;
-      Prec<T>::st4(lds + off, re);
-      Prec<T>::st4(lim + off, -im);
+    for (int b0 = 0; b0 < RL; b0 += NB) {
+      v4 re[NB], im[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) pf_rb_load<T>(re[i], im[i], M, L.w, h * RL + b0 + i, L.lane);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        int off = (16 * L.w + L.c16) * K::SD + 16 * (b0 + i) + 4 * L.g;
+        Prec<T>::st4(lds + off, re[i]);
+        Prec<T>::st4(lim + off, -im[i]);
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
