@@ -881,14 +881,24 @@ __device__ __forceinline__ void stage128(T* lds, const T* M, int h, const Lane& 
 
 // acc (+)= M B, M (or M^dag when CT) staged through LDS part by part, B this
 // wavefront's panel of a PF matrix.  Starts and ends every part with a
-// workgroup barrier, so M may have been written by any wavefront.
-template <typename T, bool CT>
+// workgroup barrier, so M may have been written by any wavefront.  G3 selects
+// the three-product form of the complex product (as cgemm3m: T1 in acc.re,
+// T3 in acc.im starting at acc.im + acc.re, T2 apart).
+template <typename T, bool CT, bool G3 = false>
 __device__ __forceinline__ void gemm128(Panel<T, 128>& acc, T* lds, const T* M, const T* B, const Lane& L,
                                         bool zero_acc) {
   using K = K128<T>;
   using v4 = typename Prec<T>::v4;
   const T* lim = lds + K::D * K::SD;
   if (zero_acc) panel_zero(acc);
+  v4 t2[G3 ? K::RB : 1];
+  if constexpr (G3) {
+#pragma unroll
+    for (int rb = 0; rb < K::RB; ++rb) {
+      t2[rb] = (v4){0, 0, 0, 0};
+      if (!zero_acc) acc.im[rb] += acc.re[rb];
+    }
+  }
   const int base = L.c16 * K::SD + 4 * L.g;
 #pragma unroll
   for (int h = 0; h < K::HALVES; ++h) {
@@ -912,16 +922,34 @@ __device__ __forceinline__ void gemm128(Panel<T, 128>& acc, T* lds, const T* M, 
         ai[cur ^ 1] = Prec<T>::ld4(lim + off);
         if (mb == 0 && kbl + 1 < K::KBH) pf_rb_load<T>(br[kcur ^ 1], bi[kcur ^ 1], B, L.w, h * K::KBH + kbl + 1, L.lane);
       }
+      if constexpr (G3) {
+        const v4 as = ar[cur] + ai[cur];
+        const v4 bs = br[kcur] + bi[kcur];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const T b_r = br[kcur][r];
-        const T b_i = bi[kcur][r];
-        acc.re[mb] = Prec<T>::mfma(ar[cur][r], b_r, acc.re[mb]);
-        acc.im[mb] = Prec<T>::mfma(ar[cur][r], b_i, acc.im[mb]);
-        acc.re[mb] = Prec<T>::mfma(-ai[cur][r], b_i, acc.re[mb]);
-        acc.im[mb] = Prec<T>::mfma(ai[cur][r], b_r, acc.im[mb]);
+        for (int r = 0; r < 4; ++r) {
+          acc.re[mb] = Prec<T>::mfma(ar[cur][r], br[kcur][r], acc.re[mb]);
+          t2[mb] = Prec<T>::mfma(ai[cur][r], bi[kcur][r], t2[mb]);
+          acc.im[mb] = Prec<T>::mfma(as[r], bs[r], acc.im[mb]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T b_r = br[kcur][r];
+          const T b_i = bi[kcur][r];
+          acc.re[mb] = Prec<T>::mfma(ar[cur][r], b_r, acc.re[mb]);
+          acc.im[mb] = Prec<T>::mfma(ar[cur][r], b_i, acc.im[mb]);
+          acc.re[mb] = Prec<T>::mfma(-ai[cur][r], b_i, acc.re[mb]);
+          acc.im[mb] = Prec<T>::mfma(ai[cur][r], b_r, acc.im[mb]);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int rb = 0; rb < K::RB; ++rb) {
+      acc.im[rb] = acc.im[rb] - acc.re[rb] - t2[rb];
+      acc.re[rb] = acc.re[rb] - t2[rb];
     }
   }
 }
@@ -1132,6 +1160,11 @@ __device__ __forceinline__ void gradient_epilogue128(const ProbDesc& P, int k, c
   }
 }
 
+// The three-product form in the FP32 expm and adjoint products at D = 128
+// (their registers allow it; the FP64 kernels already spill).
+template <typename T>
+constexpr bool k128Gauss = sizeof(T) == 4;
+
 template <typename T>
 __device__ __forceinline__ T* slot_mat(void* scratch, int i) {
   return reinterpret_cast<T*>(scratch) + ((size_t)blockIdx.x * kScratchMats + i) * K128<T>::ELEMS;
@@ -1161,16 +1194,16 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
       panel_add_identity(acc, L, (T)1);
       panel_store(SR, acc, L);
       for (int i = q - 1; i >= 2; --i) {
-        gemm128<T, false>(acc, lds, SX, SR, L, true);
+        gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR, L, true);
         panel_scale(acc, (T)(1.0 / i));
         panel_add_identity(acc, L, (T)1);
         panel_store(SR, acc, L);
       }
-      gemm128<T, false>(acc, lds, SX, SR, L, true);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR, L, true);
     }
     for (int j = 0; j < s; ++j) {
       panel_store(SR, acc, L);
-      gemm128<T, false>(acc, lds, SR, SR, L, true);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SR, SR, L, true);
       panel_axpy_pf(acc, (T)2, SR, L);
     }
     panel_store(pf_mat<T, 128>(P.delta, k - W.rg.kbase), acc, L);
@@ -1288,9 +1321,9 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     Panel<T, 128> acc;
     // W = bloc[k] (mc[c] xprev[k]^dag)
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k - W.rg.kbase), L);
-    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.mc, c), S0, L, true);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.mc, c), S0, L, true);
     panel_store(S1, acc, L);
-    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S1, L, true);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S1, L, true);
     // E = W / 2^s, R2 = E / qb
     panel_scale(acc, (T)ldexp(1.0, -s));
     panel_store(SE, acc, L);
@@ -1307,32 +1340,32 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     panel_store(SR1, acc, L);
     for (int i = qb - 1; i >= 2; --i) {
       const T inv = (T)(1.0 / i);
-      gemm128<T, false>(acc, lds, SX, SR2, L, true);
-      gemm128<T, false>(acc, lds, SE, SR1, L, false);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR2, L, true);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SR1, L, false);
       panel_scale(acc, inv);
       panel_store(SR2, acc, L);  // R2 <- (X R2 + E R1) / i  (own panel; R1 still intact)
-      gemm128<T, false>(acc, lds, SX, SR1, L, true);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR1, L, true);
       panel_scale(acc, inv);
       panel_add_identity(acc, L, (T)1);
       panel_store(SR1, acc, L);
     }
     // D1 = X R1 (into S1) when squaring follows; Q = X R2 + E R1 (into S0 and acc)
     if (s > 0) {
-      gemm128<T, false>(acc, lds, SX, SR1, L, true);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR1, L, true);
       panel_store(S1, acc, L);
     }
-    gemm128<T, false>(acc, lds, SX, SR2, L, true);
-    gemm128<T, false>(acc, lds, SE, SR1, L, false);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR2, L, true);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SR1, L, false);
     for (int j = 0; j < s; ++j) {
       panel_store(S0, acc, L);                        // Q
-      gemm128<T, false>(acc, lds, S1, S0, L, true);   // D1 Q
-      gemm128<T, false>(acc, lds, S0, S1, L, false);  // + Q D1
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S1, S0, L, true);   // D1 Q
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, S1, L, false);  // + Q D1
       panel_axpy_pf(acc, (T)2, S0, L);                // Q <- 2Q + D1 Q + Q D1
       if (j + 1 < s) {
         // Every wavefront's staging of the old Q and D1 ended before the
         // barrier inside the last product, so own panels may be replaced.
         panel_store(S0, acc, L);
-        gemm128<T, false>(acc, lds, S1, S1, L, true);
+        gemm128<T, false, k128Gauss<T>>(acc, lds, S1, S1, L, true);
         panel_axpy_pf(acc, (T)2, S1, L);              // D1 <- 2 D1 + D1^2
         panel_store(S1, acc, L);
         panel_load(acc, S0, L);
