@@ -170,15 +170,14 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
-template <typename T, int D, typename Ops, int G>
+template <typename T, int D, typename Ops>
 __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk) {
   // The matrix is read as D^2/4 chunks of four consecutive row elements;
   // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
-  // lanes of one 16-byte load read consecutive chunks.  Chunks are written to
-  // LDS four columns at a time.  The controls are read G at a time so that
-  // their load latencies overlap; indices past the last control are clamped
-  // to it and weighted by zero, which leaves every sum unchanged.  When hk is
-  // not null, H_k itself is also written there (planar, row-major).
+  // lanes of one 16-byte load read consecutive chunks, and a control's loads
+  // are all in flight together.  Chunks are written to LDS four columns at a
+  // time.  When hk is not null, H_k itself is also written there (planar,
+  // row-major) for the adjoint pass.
   using v4 = typename Prec<T>::v4;
   constexpr int NV = D / 16;
   constexpr int NT = 4 * D;
@@ -190,27 +189,20 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
     hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
   }
-  for (int j0 = 0; j0 < P.m; j0 += G) {
-    v4 ar[G][NV], ai[G][NV];
-    T uw[G];
+  for (int j = 0; j < P.m; ++j) {
+    const T uj = (T)P.u[(size_t)j * P.N + k];
+    const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+    v4 ar[NV], ai[NV];
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj) {
-      const int j = min(j0 + jj, P.m - 1);
-      uw[jj] = j0 + jj < P.m ? (T)P.u[(size_t)j * P.N + k] : (T)0;
-      const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        ar[jj][v] = Prec<T>::ld4(Hj + 4 * NT * v);
-        ai[jj][v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
-      }
+    for (int v = 0; v < NV; ++v) {
+      ar[v] = Prec<T>::ld4(Hj + 4 * NT * v);
+      ai[v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
     }
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        hr[v] += uw[jj] * ar[jj][v];
-        hi[v] += uw[jj] * ai[jj][v];
-      }
+    for (int v = 0; v < NV; ++v) {
+      hr[v] += uj * ar[v];
+      hi[v] += uj * ai[v];
+    }
   }
   const T f = (T)(sgn * c);
 #pragma unroll
@@ -224,8 +216,8 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
   }
 }
 
-// The slice's H_k as stored by k_expm, scaled and written to LDS exactly as
-// assemble() writes it (the same values bit for bit).
+// The slice's H_k as stored by k_expm, scaled and written to LDS as
+// assemble() writes it.
 template <typename T, int D, typename Ops>
 __device__ __forceinline__ void load_hamiltonian(void* lds, const T* hk, double c, double sgn) {
   using v4 = typename Prec<T>::v4;
@@ -454,8 +446,8 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
-  T* hk = (P.hk && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
-  assemble<T, D, Ops, 1>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
+  T* hk = (P.flags & RUN_GRAD) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
+  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
@@ -726,8 +718,7 @@ void k_adjoint(Work W) {
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
   Ops::store(lds[1], R2, L);
-  if (P.hk) load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
-  else assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
+  load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
   __syncthreads();
   const void* X = lds[0];
   const void* E = lds[1];
@@ -1184,7 +1175,7 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     __syncthreads();
-    T* hk = (P.hk && (P.flags & RUN_GRAD)) ? pf_mat<T, 128>(P.hk, k - W.rg.kbase) : nullptr;
+    T* hk = (P.flags & RUN_GRAD) ? pf_mat<T, 128>(P.hk, k - W.rg.kbase) : nullptr;
     assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0, hk);
     __syncthreads();
     Panel<T, 128> acc;
@@ -1331,8 +1322,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     panel_store(SR2, acc, L);
     // X = A^dag / 2^s, R1 = I + X / qb
     __syncthreads();
-    if (P.hk) load_hamiltonian128<T>(SX, pf_mat<T, 128>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
-    else assemble128<T>(SX, P, k, ldexp(P.dt, -s), -1.0, nullptr);
+    load_hamiltonian128<T>(SX, pf_mat<T, 128>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
     __syncthreads();
     panel_load(acc, SX, L);
     panel_scale(acc, (T)(1.0 / qb));

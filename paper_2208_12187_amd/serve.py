@@ -80,6 +80,19 @@ def summary(res) -> dict:
             "requests_per_s": round(res["requests_per_s"], 1)}
 
 
+def per_d(res, problems) -> dict:
+    """Latency percentiles and slice-steps of the requests of each dimension."""
+    lat = res["latency"]
+    ds = np.array([p.d for p in problems])
+    out = {}
+    for d in sorted(set(ds.tolist())):
+        sel = ds == d
+        out[str(d)] = {"requests": int(sel.sum()), "p50_ms": round(1e3 * float(np.percentile(lat[sel], 50)), 3),
+                       "p99_ms": round(1e3 * float(np.percentile(lat[sel], 99)), 3),
+                       "slice_steps": int(sum(p.N for p, s in zip(problems, sel) if s))}
+    return out
+
+
 def build_requests(n, seed=5, N_range=(100, 2000)):
     """The serving workload: trace entries (d, N) and their problems."""
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -123,7 +136,8 @@ def main(argv=None):
     out = {"requests": n, "precision": args.precision, "capacity_req_per_s": round(capacity, 1),
            "capacity_slice_steps_per_s": round(cap["slice_steps_per_s"], 1),
            "arrival_rate_req_per_s": round(rate, 1), "batched": summary(mix), "one_at_a_time": summary(alone),
-           "max_abs_dF_batched_vs_alone": float(np.max(np.abs(mix["F"] - alone["F"])))}
+           "max_abs_dF_batched_vs_alone": float(np.max(np.abs(mix["F"] - alone["F"]))),
+           "per_d": {"batched": per_d(mix, problems), "one_at_a_time": per_d(alone, problems)}}
     print(json.dumps(out), flush=True)
 
 

@@ -95,3 +95,6 @@ def test_engine_poisson_replay_reports_latency(gpu_lib):
     print(f"[serving] replay: {s}", flush=True)
     assert s["p50_ms"] > 0 and s["p99_ms"] >= s["p50_ms"]
     assert np.all(res["latency"] > 0)
+    by_d = serve.per_d(res, probs)
+    assert sum(v["requests"] for v in by_d.values()) == len(probs)
+    assert sum(v["slice_steps"] for v in by_d.values()) == sum(p.N for p in probs)
