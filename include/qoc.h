@@ -64,8 +64,8 @@ typedef struct {
   int32_t precision;      /* qoc_precision; default QOC_FP64 */
   int32_t validate;       /* nonzero: host entry points check Hermiticity and finiteness */
   uint64_t hbm_budget;    /* bytes for the per-slice and per-chunk arrays of a call
-                             (stored propagators and slice Hamiltonians);
-                             0 = no limit.
+                             (stored propagators, and the slice Hamiltonians
+                             at d > 16); 0 = no limit.
                              When those arrays exceed it, slices are
                              processed in checkpoint segments and recomputed
                              for the gradient pass (same results, more work). */
@@ -157,8 +157,8 @@ const char* qoc_stage_name(int stage);
  * Requests are queued by qoc_engine_submit (host inputs are copied into the
  * engine's pinned staging before it returns) and admitted in FIFO order
  * while their device footprint (qoc_engine_footprint: inputs, outputs and
- * the per-slice arrays of the path, about 4 N D^2 c bytes with c the bytes
- * of one complex element) fits the
+ * the per-slice arrays of the path, about 4 N D^2 c bytes at D >= 32 and
+ * 3 N D^2 c at D = 16, with c the bytes of one complex element) fits the
  * engine's device pool and one of max_active descriptor slots is free.
  * Admitted requests are grouped by padded dimension D (16, 32, 64, 128); each
  * group has its own stream and a captured graph of the path's kernels that a

@@ -3,7 +3,7 @@
 //
 // Requests wait in a FIFO queue and are admitted in order while their device
 // footprint (inputs, outputs and the per-problem workspace, about
-// 4 N D^2 c bytes of per-slice arrays) fits the engine's device arena and
+// 4 N D^2 c bytes of per-slice arrays at D >= 32) fits the engine's device arena and
 // a descriptor slot is free.  Admitted requests are grouped by padded
 // dimension D; each D bucket owns a stream and a hipGraph of the seven
 // persistent stage kernels, captured once, whose item counts, prefix sums

@@ -33,7 +33,7 @@ struct ProbDesc {
   double* norms;      // m+1 one-norms of H0, Hc[j] (FP64)
   int* sq;            // per slice: s | q << 8 | qb << 16
   void* delta;        // N PF matrices: U_k - I
-  void* hk;           // N planar matrices: H_k, kept by the expm pass for the adjoint
+  void* hk;           // N planar matrices: H_k, kept by the expm pass for the adjoint (D >= 32)
   void* xprev;        // N PF matrices: U_{k-1} ... U_{k0}   (I at a chunk start)
   void* bloc;         // N PF matrices: U_{k+1}^dag ... U_{k1-1}^dag (I at a chunk end)
   void* tf;           // P PF matrices: forward chunk totals
@@ -131,15 +131,15 @@ struct Layout {
   int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
   size_t Hint, Vint, norms, sq, delta, hk, xprev, bloc, tf, tb, cf, cb, mc, small;
-  int per_slice;  // per-slice arrays: delta, hk, xprev, bloc
+  int per_slice;  // per-slice arrays: delta, xprev, bloc, and hk at D >= 32
   size_t per_prob;
   size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
   size_t total;
 };
 
 // hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
-// batch: the four per-slice arrays (three stored propagators and the slice
-// Hamiltonians) plus the five per-chunk arrays.  When the
+// batch: the per-slice arrays (three stored propagators, and the slice
+// Hamiltonians at D >= 32) plus the five per-chunk arrays.  When the
 // full arrays do not fit, slices are processed in segments of G chunks whose
 // per-slice arrays are recomputed for the adjoint pass (sqrt(N)
 // checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
@@ -151,7 +151,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.P = (N + Lo.L - 1) / Lo.L;
   const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
   Lo.G = Lo.P;
-  Lo.per_slice = 4;
+  Lo.per_slice = Lo.D >= 32 ? 4 : 3;
   const double full = (double)B * ((double)Lo.per_slice * N + 5.0 * Lo.P) * (double)mat;
   if (hbm_budget > 0 && full > (double)hbm_budget) {
     const double avail = (double)hbm_budget / B - 5.0 * Lo.P * (double)mat;
@@ -165,7 +165,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
   Lo.sq = o; o = align_up(o + (size_t)N * 4);
   Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
-  Lo.hk = o; o = align_up(o + (size_t)Lo.W * mat);
+  Lo.hk = o; o = align_up(o + (Lo.per_slice == 4 ? (size_t)Lo.W * mat : 0));
   Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
@@ -208,7 +208,7 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.norms = reinterpret_cast<double*>(pb + Lo.norms);
   P.sq = reinterpret_cast<int*>(pb + Lo.sq);
   P.delta = pb + Lo.delta;
-  P.hk = pb + Lo.hk;
+  P.hk = Lo.per_slice == 4 ? pb + Lo.hk : nullptr;
   P.xprev = pb + Lo.xprev;
   P.bloc = pb + Lo.bloc;
   P.tf = pb + Lo.tf;

@@ -170,14 +170,15 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
-template <typename T, int D, typename Ops>
+template <typename T, int D, typename Ops, int G = 1>
 __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk) {
   // The matrix is read as D^2/4 chunks of four consecutive row elements;
   // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
-  // lanes of one 16-byte load read consecutive chunks, and a control's loads
-  // are all in flight together.  Chunks are written to LDS four columns at a
-  // time.  When hk is not null, H_k itself is also written there (planar,
-  // row-major) for the adjoint pass.
+  // lanes of one 16-byte load read consecutive chunks.  The loads of G
+  // controls are in flight together; indices past the last control are
+  // clamped to it and weighted by zero, which leaves every sum unchanged.
+  // Chunks are written to LDS four columns at a time.  When hk is not null,
+  // H_k itself is also written there (planar, row-major) for the adjoint.
   using v4 = typename Prec<T>::v4;
   constexpr int NV = D / 16;
   constexpr int NT = 4 * D;
@@ -189,20 +190,27 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
     hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
   }
-  for (int j = 0; j < P.m; ++j) {
-    const T uj = (T)P.u[(size_t)j * P.N + k];
-    const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
-    v4 ar[NV], ai[NV];
+  for (int j0 = 0; j0 < P.m; j0 += G) {
+    v4 ar[G][NV], ai[G][NV];
+    T uw[G];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      ar[v] = Prec<T>::ld4(Hj + 4 * NT * v);
-      ai[v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = min(j0 + jj, P.m - 1);
+      uw[jj] = j0 + jj < P.m ? (T)P.u[(size_t)j * P.N + k] : (T)0;
+      const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ar[jj][v] = Prec<T>::ld4(Hj + 4 * NT * v);
+        ai[jj][v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+      }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      hr[v] += uj * ar[v];
-      hi[v] += uj * ai[v];
-    }
+    for (int jj = 0; jj < G; ++jj)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        hr[v] += uw[jj] * ar[jj][v];
+        hi[v] += uw[jj] * ai[jj][v];
+      }
   }
   const T f = (T)(sgn * c);
 #pragma unroll
@@ -425,18 +433,21 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
 // Horner in delta form: R_q = I + X/q, R_i = I + X R_{i+1} / i, Delta = X R_2
 // (X = A_k / 2^s), then s squarings Delta <- 2 Delta + Delta^2.
-// The expm kernel takes the three-product form in FP32, where the extra
-// registers leave its occupancy unchanged, and not in FP64, where they would
-// halve it at D = 64.
-template <typename T, int D, typename Ops>
-__device__ __forceinline__ void expm_gemm(Panel<T, D>& acc, const void* lds, const Panel<T, D>& P, const Lane& L,
-                                          bool zero_acc) {
-  if constexpr (sizeof(T) == 4) Ops::gemm3(acc, lds, P, L, zero_acc);
-  else Ops::gemm(acc, lds, P, L, zero_acc);
-}
+// The expm and scan kernels take the three-product form (Ops::gemm3) at
+// D >= 32 with a floor of two waves per SIMD, which keeps the extra registers
+// of that form from lowering their occupancy.
+template <int D>
+constexpr int kMinWaves = D >= 32 ? 2 : 1;
+
+// The slice Hamiltonians are kept for the adjoint at D >= 32.  At D = 16 the
+// adjoint re-assembles H_k from the (L2-resident) controls, which costs less
+// than writing and reading it back through HBM.
+template <int D>
+constexpr bool kKeepH = D >= 32;
 
 template <typename T, int D, typename Ops, bool PERSIST>
-__global__ __launch_bounds__(4 * D) void k_expm(Work W) {
+__global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
+void k_expm(Work W) {
   __shared__ __align__(16) unsigned char lds[Ops::BYTES];
   Lane L;
   const Items I(W);
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
   const ProbDesc& P = W.descs[I.desc(p)];
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
-  T* hk = (P.flags & RUN_GRAD) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
+  T* hk = (kKeepH<D> && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
   assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
   __syncthreads();
   Panel<T, D> R, acc;
@@ -455,19 +466,19 @@ __global__ __launch_bounds__(4 * D) void k_expm(Work W) {
     panel_scale(R, (T)(1.0 / q));
     panel_add_identity(R, L, (T)1);
     for (int i = q - 1; i >= 2; --i) {
-      expm_gemm<T, D, Ops>(acc, lds, R, L, true);
+      Ops::gemm3(acc, lds, R, L, true);
       R = acc;
       panel_scale(R, (T)(1.0 / i));
       panel_add_identity(R, L, (T)1);
     }
-    expm_gemm<T, D, Ops>(acc, lds, R, L, true);
+    Ops::gemm3(acc, lds, R, L, true);
     R = acc;
   }
   for (int j = 0; j < s; ++j) {
     __syncthreads();
     Ops::store(lds, R, L);
     __syncthreads();
-    expm_gemm<T, D, Ops>(acc, lds, R, L, true);
+    Ops::gemm3(acc, lds, R, L, true);
     panel_axpby(R, (T)1, acc, (T)2);
   }
   panel_store(pf_mat<T, D>(P.delta, k - W.rg.kbase), R, L);
@@ -560,7 +571,8 @@ __device__ __forceinline__ void reunitarise(const ProbDesc& P, Panel<float, D>& 
 // bloc[k] = S before slice k is applied and the chunk total.  Each step is
 // S <- S + Delta S (or Delta^dag S) with Delta staged in LDS, double-buffered.
 template <typename T, int D, typename Ops, bool PERSIST>
-__global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
+__global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
+void k_scan_local(Work W) {
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
   __shared__ double red[D / 16];
   Lane L;
@@ -584,7 +596,7 @@ __global__ __launch_bounds__(4 * D) void k_scan_local(Work W) {
     if (i + 1 < n) panel_load(nxt, pf_mat<T, D>(P.delta, kn - W.rg.kbase), L);
     panel_store(pf_mat<T, D>(bwd ? P.bloc : P.xprev, k - W.rg.kbase), S, L);
     __syncthreads();
-    Ops::gemm(acc, buf, S, L, true);
+    Ops::gemm3(acc, buf, S, L, true);
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
   }
@@ -718,7 +730,8 @@ void k_adjoint(Work W) {
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
   Ops::store(lds[1], R2, L);
-  load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
+  if constexpr (kKeepH<D>) load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
+  else assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
   __syncthreads();
   const void* X = lds[0];
   const void* E = lds[1];

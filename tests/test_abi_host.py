@@ -105,7 +105,8 @@ def test_slice_plan_prefers_fewer_products():
 
 def test_engine_footprint_tracks_the_stored_propagators():
     """About 4 N D^2 c bytes of per-slice arrays (three stored propagators and
-    the slice Hamiltonians kept for the adjoint) dominate a request."""
+    the slice Hamiltonians kept for the adjoint) dominate a request at
+    D >= 32, 3 N D^2 c at D = 16."""
     L = qoc.lib()
     for prec, c in (("fp32", 8), ("fp64", 16)):
         f = qoc.Engine.footprint(prec, 64, 12, 2000)
@@ -113,7 +114,8 @@ def test_engine_footprint_tracks_the_stored_propagators():
         assert core < f < 1.2 * core
         assert qoc.Engine.footprint(prec, 64, 12, 1000) < f
         # d = 3 is padded to 16: same stored propagators, smaller inputs
-        assert 4 * 100 * 16 * 16 * c < qoc.Engine.footprint(prec, 3, 6, 100) < qoc.Engine.footprint(prec, 16, 6, 100)
+        assert 3 * 100 * 16 * 16 * c < qoc.Engine.footprint(prec, 3, 6, 100) < qoc.Engine.footprint(prec, 16, 6, 100)
+        assert qoc.Engine.footprint(prec, 16, 6, 100) < 1.3 * 3 * 100 * 16 * 16 * c + (1 << 20)
         f128 = qoc.Engine.footprint(prec, 128, 14, 1000)
         assert 4 * 1000 * 128 * 128 * c < f128 < 1.2 * 4 * 1000 * 128 * 128 * c
     assert L.qoc_engine_footprint(1, 0, 1, 1) == 0

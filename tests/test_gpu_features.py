@@ -24,7 +24,7 @@ def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec, seg):
     mat = 2 * D * D * (8 if prec == "fp64" else 4)
     L = int(np.ceil(np.sqrt(N)))
     P = -(-N // L)
-    per_slice = 4  # three stored propagators and the slice Hamiltonians
+    per_slice = 4 if D >= 32 else 3  # stored propagators, and the slice Hamiltonians at D >= 32
     budget = 2 * (5 * P + seg * per_slice * L + 1) * mat  # segments of `seg` chunks
     small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=budget)
     assert small.ws_bytes < full.ws_bytes
