@@ -37,21 +37,22 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     direction; adjoint 3 (qb + s) - 2 (two for W, three per block Horner
     step or squaring, less the top-left blocks the last step does not need).
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
-    the three-product (Gauss) form, which the adjoint (FP32 at d >= 32, FP64
-    at 32 <= d <= 64) and the FP32 expm (d >= 32) use.  The split-BF16 path
-    issues three BF16 products per real one, 24 d^3 BF16 flops per complex
-    product.  Assembly and the gradient inner products run on the vector ALU
-    and are not counted."""
+    the three-product (Gauss) form.  FP32 and FP64 use the latter in every
+    stage at 32 <= d <= 64, and FP32 also in the expm and adjoint at d = 128.
+    The split-BF16 path issues three BF16 products per real one, 24 d^3 BF16
+    flops per complex product.  Assembly and the gradient inner products run
+    on the vector ALU and are not counted."""
     s, q, qb = plan[:, 0].astype(np.float64), plan[:, 1].astype(np.float64), plan[:, 2].astype(np.float64)
     G4, G3 = 8.0 * d ** 3, 6.0 * d ** 3
     if prec == "bf16x3":
         G4 = G3 = 24.0 * d ** 3
-    three_adj = (prec == "fp32" and d >= 32) or (prec == "fp64" and 32 <= d <= 64)
-    three_expm = prec == "fp32" and d >= 32
-    g_adj = G3 if three_adj else G4
-    g_expm = G3 if three_expm else G4
+    mid = prec in ("fp32", "fp64") and 32 <= d <= 64
+    big32 = prec == "fp32" and d > 64
+    g_adj = G3 if (mid or big32) else G4
+    g_expm = G3 if (mid or big32) else G4
+    g_scan = G3 if mid else G4
     n_adj = 3 * (qb + s) - 2
-    return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * G4 * len(s)),
+    return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * g_scan * len(s)),
             "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
 
 

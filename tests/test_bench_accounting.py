@@ -34,14 +34,16 @@ def test_three_product_form_is_counted_where_used():
     n_adj = 10 + 13
     assert f32["adjoint"] == 6.0 * d ** 3 * n_adj and f64["adjoint"] == 6.0 * d ** 3 * n_adj
     assert b16["adjoint"] == 24.0 * d ** 3 * n_adj and b16["adjoint_8d3"] == 8.0 * d ** 3 * n_adj
-    # expm: q - 1 + s products, three-product form in FP32 only
-    assert f32["expm"] == 6.0 * d ** 3 * (2 + 3) and f64["expm"] == 8.0 * d ** 3 * (2 + 3)
-    assert f32["scan"] == 2 * 8.0 * d ** 3 * 2
+    # expm: q - 1 + s products; scans: one per direction; all three-product
+    assert f32["expm"] == 6.0 * d ** 3 * (2 + 3) and f64["expm"] == 6.0 * d ** 3 * (2 + 3)
+    assert f32["scan"] == 2 * 6.0 * d ** 3 * 2 and f64["scan"] == 2 * 6.0 * d ** 3 * 2
+    assert b16["scan"] == 2 * 24.0 * d ** 3 * 2
     # d = 16 uses the four-product form everywhere; at d = 128 the FP32 expm
     # and adjoint use the three-product form and FP64 does not
     f = bench.slice_flops(plan, 16, 8, "fp32")
     assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * 16 ** 3 * 5
     f = bench.slice_flops(plan, 128, 14, "fp32")
     assert f["adjoint"] == 6.0 * 128 ** 3 * n_adj and f["expm"] == 6.0 * 128 ** 3 * 5
+    assert f["scan"] == 2 * 8.0 * 128 ** 3 * 2
     f = bench.slice_flops(plan, 128, 14, "fp64")
     assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * 128 ** 3 * 5
