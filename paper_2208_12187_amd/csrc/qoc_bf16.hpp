@@ -4,7 +4,8 @@
 // Every FP32 value x is split into hi = bf16(x) and lo = bf16(x - hi)
 // (round to nearest even; x - hi is exact in FP32), and a real product is
 // taken as A_hi B_hi + A_hi B_lo + A_lo B_hi, dropping A_lo B_lo (relative
-// size about 2^-16).  A complex product is four real ones, so one
+// size about 2^-16).  A complex product is taken as four real ones (the
+// three-product form would need BF16 splits of Ar + Ai as well), so one
 // (k step, row block) step issues 12 MFMAs, each of K = 32.
 //
 // Register panels stay FP32 in the accumulator layout (rows 16 rb + 4g + r).

@@ -12,8 +12,9 @@
 // stands for matrix row 16 rb + rowmap(r, g).  The A operand is read from LDS
 // with the matching permutation of its columns, so chained products
 // (Horner steps, scan steps) keep their state in registers and only the
-// left factor is staged in LDS.  Complex products use four real MFMAs:
-//   Re += Ar Br - Ai Bi,  Im += Ar Bi + Ai Br.
+// left factor is staged in LDS.  Complex products use four real MFMA
+// products (cgemm), Re += Ar Br - Ai Bi and Im += Ar Bi + Ai Br, or three
+// (cgemm3m, the Gauss form below).
 //
 // LDS matrices are row-major with separate real and imaginary planes, a row
 // stride of D + pad elements (16 bytes of padding) and, within each 16-column
@@ -36,6 +37,22 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+// Global-memory accesses go through address space 1, so that the compiler
+// issues global_* instructions.  Through a generic pointer it issues flat_*
+// ones, which may also address LDS; it then has to wait for every
+// outstanding memory operation around them (a prefetch issued before a store
+// would be waited for at once).
+#define QOC_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const QOC_GLOBAL T* gp(const T* p) {
+  return (const QOC_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ QOC_GLOBAL T* gp(T* p) {
+  return (QOC_GLOBAL T*)p;
+}
+
 template <typename T>
 struct Prec;
 
@@ -50,6 +67,9 @@ struct Prec<float> {
   }
   __device__ static __forceinline__ v4 ld4(const float* p) { return *reinterpret_cast<const f4*>(p); }
   __device__ static __forceinline__ void st4(float* p, v4 v) { *reinterpret_cast<f4*>(p) = v; }
+  // the same from / to global memory
+  __device__ static __forceinline__ v4 gld4(const float* p) { return *(const QOC_GLOBAL f4*)p; }
+  __device__ static __forceinline__ void gst4(float* p, v4 v) { *(QOC_GLOBAL f4*)p = v; }
 };
 
 template <>
@@ -73,6 +93,20 @@ struct Prec<double> {
     lo.x = v.x; lo.y = v.y; hi.x = v.z; hi.y = v.w;
     *reinterpret_cast<d2*>(p) = lo;
     *reinterpret_cast<d2*>(p + 2) = hi;
+  }
+  // the same from / to global memory
+  __device__ static __forceinline__ v4 gld4(const double* p) {
+    d2 lo = *(const QOC_GLOBAL d2*)p;
+    d2 hi = *(const QOC_GLOBAL d2*)(p + 2);
+    v4 v;
+    v.x = lo.x; v.y = lo.y; v.z = hi.x; v.w = hi.y;
+    return v;
+  }
+  __device__ static __forceinline__ void gst4(double* p, v4 v) {
+    d2 lo, hi;
+    lo.x = v.x; lo.y = v.y; hi.x = v.z; hi.y = v.w;
+    *(QOC_GLOBAL d2*)p = lo;
+    *(QOC_GLOBAL d2*)(p + 2) = hi;
   }
 };
 
@@ -344,16 +378,16 @@ __device__ __forceinline__ void panel_load(Panel<T, D>& P, const T* M, const Lan
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
-      P.re[rb] = *reinterpret_cast<const f4*>(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane));
-      P.im[rb] = *reinterpret_cast<const f4*>(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane));
+      P.re[rb] = *(const QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane));
+      P.im[rb] = *(const QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane));
     }
   } else {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
 #pragma unroll
       for (int plane = 0; plane < 2; ++plane) {
-        d2 a = *reinterpret_cast<const d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane));
-        d2 b = *reinterpret_cast<const d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane));
+        d2 a = *(const QOC_GLOBAL d2*)(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane));
+        d2 b = *(const QOC_GLOBAL d2*)(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane));
         d4 v;
         v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
         if (plane == 0) P.re[rb] = v; else P.im[rb] = v;
@@ -367,8 +401,8 @@ __device__ __forceinline__ void panel_store(T* M, const Panel<T, D>& P, const La
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
-      *reinterpret_cast<f4*>(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane)) = P.re[rb];
-      *reinterpret_cast<f4*>(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane)) = P.im[rb];
+      *(QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane)) = P.re[rb];
+      *(QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 1, 4 * rb, L.lane)) = P.im[rb];
     }
   } else {
 #pragma unroll
@@ -378,8 +412,8 @@ __device__ __forceinline__ void panel_store(T* M, const Panel<T, D>& P, const La
         d4 v = plane == 0 ? P.re[rb] : P.im[rb];
         d2 a, b;
         a.x = v.x; a.y = v.y; b.x = v.z; b.y = v.w;
-        *reinterpret_cast<d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane)) = a;
-        *reinterpret_cast<d2*>(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane)) = b;
+        *(QOC_GLOBAL d2*)(M + pf_index<T, D>(L.w, plane, 4 * rb, L.lane)) = a;
+        *(QOC_GLOBAL d2*)(M + pf_index<T, D>(L.w, plane, 4 * rb + 2, L.lane)) = b;
       }
     }
   }

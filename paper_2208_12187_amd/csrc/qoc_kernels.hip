@@ -158,9 +158,9 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
   for (int item = blockIdx.x * 256 + threadIdx.x; item < I.total; item += gridDim.x * 256) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[I.desc(p)];
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     double th = P.norms[0];
-    for (int j = 0; j < P.m; ++j) th = fma(fabs(P.u[(size_t)j * P.N + k]), P.norms[j + 1], th);
+    for (int j = 0; j < P.m; ++j) th = fma(fabs(gp(P.u)[(size_t)j * P.N + k]), gp(P.norms)[j + 1], th);
     th *= P.dt;
     P.sq[k] = pack_plan(choose_plan(th, ur, grad != 0));
   }
@@ -187,8 +187,8 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
   v4 hr[NV], hi[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
-    hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
+    hr[v] = Prec<T>::gld4(H + e0 + 4 * NT * v);
+    hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
   }
   for (int j0 = 0; j0 < P.m; j0 += G) {
     v4 ar[G][NV], ai[G][NV];
@@ -196,12 +196,12 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
       const int j = min(j0 + jj, P.m - 1);
-      uw[jj] = j0 + jj < P.m ? (T)P.u[(size_t)j * P.N + k] : (T)0;
+      uw[jj] = j0 + jj < P.m ? (T)gp(P.u)[(size_t)j * P.N + k] : (T)0;
       const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        ar[jj][v] = Prec<T>::ld4(Hj + 4 * NT * v);
-        ai[jj][v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+        ar[jj][v] = Prec<T>::gld4(Hj + 4 * NT * v);
+        ai[jj][v] = Prec<T>::gld4(Hj + D * D + 4 * NT * v);
       }
     }
 #pragma unroll
@@ -218,8 +218,8 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     const int e = e0 + 4 * NT * v;
     Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
     if (hk) {
-      Prec<T>::st4(hk + e, hr[v]);
-      Prec<T>::st4(hk + D * D + e, hi[v]);
+      Prec<T>::gst4(hk + e, hr[v]);
+      Prec<T>::gst4(hk + D * D + e, hi[v]);
     }
   }
 }
@@ -235,8 +235,8 @@ __device__ __forceinline__ void load_hamiltonian(void* lds, const T* hk, double 
   v4 hr[NV], hi[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    hr[v] = Prec<T>::ld4(hk + e0 + 4 * NT * v);
-    hi[v] = Prec<T>::ld4(hk + D * D + e0 + 4 * NT * v);
+    hr[v] = Prec<T>::gld4(hk + e0 + 4 * NT * v);
+    hi[v] = Prec<T>::gld4(hk + D * D + e0 + 4 * NT * v);
   }
   const T f = (T)(sgn * c);
 #pragma unroll
@@ -359,7 +359,7 @@ __device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j
       b += rg[(2 * jj + 1) * NWAVES + w];
     }
     const double pref = 2.0 * P.dt / ((double)P.d * P.d);
-    P.grad[(size_t)(j0 + jj) * P.N + k] = pref * (P.g[0] * b - P.g[1] * a);
+    gp(P.grad)[(size_t)(j0 + jj) * P.N + k] = pref * (gp(P.g)[0] * b - gp(P.g)[1] * a);
   }
 }
 
@@ -404,8 +404,8 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
         const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-          hr[jj][q] = Prec<T>::ld4(Hj + 4 * NT * q);
-          hi[jj][q] = Prec<T>::ld4(Hj + D * D + 4 * NT * q);
+          hr[jj][q] = Prec<T>::gld4(Hj + 4 * NT * q);
+          hi[jj][q] = Prec<T>::gld4(Hj + D * D + 4 * NT * q);
         }
       }
 #pragma unroll
@@ -454,7 +454,7 @@ void k_expm(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, k;
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-  const ProbDesc& P = W.descs[I.desc(p)];
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
   T* hk = (kKeepH<D> && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
@@ -581,7 +581,7 @@ void k_scan_local(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
   split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-  const ProbDesc& P = W.descs[I.desc(p)];
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   const int k0 = c * P.L;
   const int k1 = min(P.N, k0 + P.L);
   Panel<T, D> S, nxt, acc;
@@ -593,8 +593,10 @@ void k_scan_local(Work W) {
     void* buf = lds[i & 1];
     if (bwd) Ops::store_ct(buf, nxt, L); else Ops::store(buf, nxt, L);
     const int kn = bwd ? k - 1 : k + 1;
-    if (i + 1 < n) panel_load(nxt, pf_mat<T, D>(P.delta, kn - W.rg.kbase), L);
+    // the store of S before the prefetch of the next Delta, so that the wait
+    // for the prefetch at the next step covers nothing issued after it
     panel_store(pf_mat<T, D>(bwd ? P.bloc : P.xprev, k - W.rg.kbase), S, L);
+    if (i + 1 < n) panel_load(nxt, pf_mat<T, D>(P.delta, kn - W.rg.kbase), L);
     __syncthreads();
     Ops::gemm3(acc, buf, S, L, true);
     panel_axpby(S, (T)1, acc, (T)1);
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   const int bwd = blockIdx.y;
   const Items I(W);
   for (int p = blockIdx.x; p < I.nprob; p += gridDim.x) {
-  const ProbDesc& P = W.descs[I.desc(p)];
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   Panel<T, D> S, nxt, acc;
   const int nc = P.P;
   if (bwd) panel_load(S, reinterpret_cast<const T*>(P.Vint), L); else panel_identity(S, L);
@@ -664,7 +666,7 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
   split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-  const ProbDesc& P = W.descs[I.desc(p)];
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   Panel<T, D> a, b;
   panel_load(a, pf_mat<T, D>(P.cb, c), L);
   panel_to_lds(lds[0], a, L);
@@ -705,7 +707,7 @@ void k_adjoint(Work W) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, k;
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-  const ProbDesc& P = W.descs[I.desc(p)];
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(P.sq[k], s, q, qb);
   const int c = k / P.L;
@@ -807,13 +809,13 @@ template <typename T>
 __device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Prec<T>::v4& im, const T* M, int w,
                                            int rb, int lane) {
   if constexpr (sizeof(T) == 4) {
-    re = *reinterpret_cast<const f4*>(M + pf_index<T, 128>(w, 0, 4 * rb, lane));
-    im = *reinterpret_cast<const f4*>(M + pf_index<T, 128>(w, 1, 4 * rb, lane));
+    re = *(const QOC_GLOBAL f4*)(M + pf_index<T, 128>(w, 0, 4 * rb, lane));
+    im = *(const QOC_GLOBAL f4*)(M + pf_index<T, 128>(w, 1, 4 * rb, lane));
   } else {
 #pragma unroll
     for (int plane = 0; plane < 2; ++plane) {
-      d2 a = *reinterpret_cast<const d2*>(M + pf_index<T, 128>(w, plane, 4 * rb, lane));
-      d2 b = *reinterpret_cast<const d2*>(M + pf_index<T, 128>(w, plane, 4 * rb + 2, lane));
+      d2 a = *(const QOC_GLOBAL d2*)(M + pf_index<T, 128>(w, plane, 4 * rb, lane));
+      d2 b = *(const QOC_GLOBAL d2*)(M + pf_index<T, 128>(w, plane, 4 * rb + 2, lane));
       d4 v;
       v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
       if (plane == 0) re = v; else im = v;
@@ -1021,17 +1023,17 @@ __device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, do
     v4 hr[NV], hi[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      hr[v] = Prec<T>::ld4(H + e0 + 4 * NT * v);
-      hi[v] = Prec<T>::ld4(H + D * D + e0 + 4 * NT * v);
+      hr[v] = Prec<T>::gld4(H + e0 + 4 * NT * v);
+      hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
     }
     for (int j = 0; j < P.m; ++j) {
-      const T uj = (T)P.u[(size_t)j * P.N + k];
+      const T uj = (T)gp(P.u)[(size_t)j * P.N + k];
       const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
       v4 ar[NV], ai[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        ar[v] = Prec<T>::ld4(Hj + 4 * NT * v);
-        ai[v] = Prec<T>::ld4(Hj + D * D + 4 * NT * v);
+        ar[v] = Prec<T>::gld4(Hj + 4 * NT * v);
+        ai[v] = Prec<T>::gld4(Hj + D * D + 4 * NT * v);
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -1043,8 +1045,8 @@ __device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, do
     for (int v = 0; v < NV; ++v) {
       const int e = e0 + 4 * NT * v;
       if (hk) {
-        Prec<T>::st4(hk + e, hr[v]);
-        Prec<T>::st4(hk + D * D + e, hi[v]);
+        Prec<T>::gst4(hk + e, hr[v]);
+        Prec<T>::gst4(hk + D * D + e, hi[v]);
       }
       put4_pf128<T>(out, e, f, hr[v], hi[v]);
     }
@@ -1065,8 +1067,8 @@ __device__ __forceinline__ void load_hamiltonian128(T* out, const T* hk, double 
     v4 hr[NV], hi[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      hr[v] = Prec<T>::ld4(hk + e0 + 4 * NT * v);
-      hi[v] = Prec<T>::ld4(hk + D * D + e0 + 4 * NT * v);
+      hr[v] = Prec<T>::gld4(hk + e0 + 4 * NT * v);
+      hi[v] = Prec<T>::gld4(hk + D * D + e0 + 4 * NT * v);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) put4_pf128<T>(out, e0 + 4 * NT * v, f, hr[v], hi[v]);
@@ -1139,8 +1141,8 @@ __device__ __forceinline__ void gradient_epilogue128(const ProbDesc& P, int k, c
           const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
 #pragma unroll
           for (int q = 0; q < NV; ++q) {
-            hr[jj][q] = Prec<T>::ld4(Hj + 4 * NT * q);
-            hi[jj][q] = Prec<T>::ld4(Hj + D * D + 4 * NT * q);
+            hr[jj][q] = Prec<T>::gld4(Hj + 4 * NT * q);
+            hi[jj][q] = Prec<T>::gld4(Hj + D * D + 4 * NT * q);
           }
         }
 #pragma unroll
@@ -1184,7 +1186,7 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[I.desc(p)];
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     __syncthreads();
@@ -1223,7 +1225,7 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int dirs) {
     const int bwd = item % dirs;
     int p, c;
     split_item(item / dirs, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-    const ProbDesc& P = W.descs[I.desc(p)];
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     const int k0 = c * P.L;
     const int k1 = min(P.N, k0 + P.L);
     Panel<T, 128> acc;
@@ -1257,7 +1259,7 @@ __global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratc
   const Items I(W);
   for (int item = blockIdx.x; item < I.nprob * dirs; item += gridDim.x) {
     const int bwd = item % dirs;
-    const ProbDesc& P = W.descs[I.desc(item / dirs)];
+    const ProbDesc P = W.descs[I.desc(item / dirs)];  // a copy: stores cannot alias it
     const int nc = P.P;
     Panel<T, 128> acc;
     if (!bwd) {
@@ -1293,7 +1295,7 @@ __global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, c;
     split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
-    const ProbDesc& P = W.descs[I.desc(p)];
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.cf, c), L);
     Panel<T, 128> acc;
     gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), S0, L, true);
@@ -1318,7 +1320,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
-    const ProbDesc& P = W.descs[I.desc(p)];
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
     unpack_sq(P.sq[k], s, q, qb);
     const int c = k / P.L;
