@@ -368,7 +368,7 @@ __device__ __forceinline__ void cgemm3m(Panel<T, D>& acc, const T* A, const Pane
 // ---------------------------------------------------------------- stored (PF) matrices
 
 template <typename T, int D>
-__device__ __forceinline__ int pf_index(int w, int plane, int reg, int lane) {
+__host__ __device__ constexpr int pf_index(int w, int plane, int reg, int lane) {
   constexpr int G = 16 / sizeof(T);
   return ((w * 2 + plane) * (D / 4 / G) + reg / G) * 64 * G + lane * G + reg % G;
 }

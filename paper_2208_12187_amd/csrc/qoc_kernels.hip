@@ -32,7 +32,7 @@ __device__ __forceinline__ int locate(const int* start, int n, int item) {
   int lo = 0, hi = n;
   while (hi - lo > 1) {
     int mid = (lo + hi) >> 1;
-    if (start[mid] <= item) lo = mid; else hi = mid;
+    if (gp(start)[mid] <= item) lo = mid; else hi = mid;
   }
   return lo;
 }
@@ -46,7 +46,7 @@ __device__ __forceinline__ void split_item(int item, int lo, int count, const in
     k = lo + (item - p * count);
   } else {
     p = locate(start, n, item);
-    k = item - start[p];
+    k = item - gp(start)[p];
   }
 }
 
@@ -57,8 +57,8 @@ struct Items {
   const int* slot;  // descriptor index of each problem (engine launches), else identity
   __device__ __forceinline__ explicit Items(const Work& W) {
     if (W.dyn) {
-      nprob = W.dyn[0];
-      total = W.dyn[1];
+      nprob = gp(W.dyn)[0];
+      total = gp(W.dyn)[1];
       start = W.dyn + 2;
       slot = W.dyn + 3 + nprob;
     } else {
@@ -68,7 +68,7 @@ struct Items {
       slot = nullptr;
     }
   }
-  __device__ __forceinline__ int desc(int p) const { return slot ? slot[p] : p; }
+  __device__ __forceinline__ int desc(int p) const { return slot ? gp(slot)[p] : p; }
 };
 
 template <typename T, int D>
@@ -456,7 +456,7 @@ void k_expm(Work W) {
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
-  unpack_sq(P.sq[k], s, q, qb);
+  unpack_sq(gp(P.sq)[k], s, q, qb);
   T* hk = (kKeepH<D> && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
   assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
   __syncthreads();
@@ -709,7 +709,7 @@ void k_adjoint(Work W) {
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
-  unpack_sq(P.sq[k], s, q, qb);
+  unpack_sq(gp(P.sq)[k], s, q, qb);
   const int c = k / P.L;
   Panel<T, D> R1, R2, A1, A2;
 
@@ -804,18 +804,26 @@ struct K128 {
   static constexpr int WPH = NW / HALVES;           // panels per staged part
 };
 
-// Row block rb of this wavefront's panel of a PF matrix.
+// Row block rb of this wavefront's panel of a PF matrix.  The element offset
+// passes through an empty asm statement, so that each load's address is
+// formed where the load is issued: otherwise the compiler precomputes the
+// 64-bit addresses of every row block of a product and spills them, and each
+// reload waits for all outstanding loads.
 template <typename T>
 __device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Prec<T>::v4& im, const T* M, int w,
                                            int rb, int lane) {
+  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);  // offset of the imaginary plane
+  int off = pf_index<T, 128>(w, 0, 4 * rb, lane);
+  asm volatile("" : "+v"(off));
   if constexpr (sizeof(T) == 4) {
-    re = *(const QOC_GLOBAL f4*)(M + pf_index<T, 128>(w, 0, 4 * rb, lane));
-    im = *(const QOC_GLOBAL f4*)(M + pf_index<T, 128>(w, 1, 4 * rb, lane));
+    re = *(const QOC_GLOBAL f4*)(M + off);
+    im = *(const QOC_GLOBAL f4*)(M + off + PLANE);
   } else {
+    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);  // offset of registers 2 and 3
 #pragma unroll
     for (int plane = 0; plane < 2; ++plane) {
-      d2 a = *(const QOC_GLOBAL d2*)(M + pf_index<T, 128>(w, plane, 4 * rb, lane));
-      d2 b = *(const QOC_GLOBAL d2*)(M + pf_index<T, 128>(w, plane, 4 * rb + 2, lane));
+      d2 a = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE);
+      d2 b = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE + R2);
       d4 v;
       v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
       if (plane == 0) re = v; else im = v;
@@ -1188,7 +1196,7 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
-    unpack_sq(P.sq[k], s, q, qb);
+    unpack_sq(gp(P.sq)[k], s, q, qb);
     __syncthreads();
     T* hk = (P.flags & RUN_GRAD) ? pf_mat<T, 128>(P.hk, k - W.rg.kbase) : nullptr;
     assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0, hk);
@@ -1322,7 +1330,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
-    unpack_sq(P.sq[k], s, q, qb);
+    unpack_sq(gp(P.sq)[k], s, q, qb);
     const int c = k / P.L;
     Panel<T, 128> acc;
     // W = bloc[k] (mc[c] xprev[k]^dag)
