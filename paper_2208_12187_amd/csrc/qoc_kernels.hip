@@ -224,25 +224,34 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
   }
 }
 
-// The slice's H_k as stored by k_expm, scaled and written to LDS as
-// assemble() writes it.
-template <typename T, int D, typename Ops>
-__device__ __forceinline__ void load_hamiltonian(void* lds, const T* hk, double c, double sgn) {
-  using v4 = typename Prec<T>::v4;
-  constexpr int NV = D / 16;
+// The slice's H_k as stored by k_expm: ham_load issues the loads of this
+// thread's chunks (the same chunks as assemble), ham_put writes them to LDS,
+// scaled, as assemble() writes its result.
+template <typename T, int D>
+struct HamRegs {
+  typename Prec<T>::v4 hr[D / 16], hi[D / 16];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void ham_load(HamRegs<T, D>& H, const T* hk) {
   constexpr int NT = 4 * D;
   const int e0 = 4 * threadIdx.x;
-  v4 hr[NV], hi[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    hr[v] = Prec<T>::gld4(hk + e0 + 4 * NT * v);
-    hi[v] = Prec<T>::gld4(hk + D * D + e0 + 4 * NT * v);
+  for (int v = 0; v < D / 16; ++v) {
+    H.hr[v] = Prec<T>::gld4(hk + e0 + 4 * NT * v);
+    H.hi[v] = Prec<T>::gld4(hk + D * D + e0 + 4 * NT * v);
   }
+}
+
+template <typename T, int D, typename Ops>
+__device__ __forceinline__ void ham_put(void* lds, const HamRegs<T, D>& H, double c, double sgn) {
+  constexpr int NT = 4 * D;
+  const int e0 = 4 * threadIdx.x;
   const T f = (T)(sgn * c);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
+  for (int v = 0; v < D / 16; ++v) {
     const int e = e0 + 4 * NT * v;
-    Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);
+    Ops::put4(lds, e / D, e % D, f * H.hi[v], -f * H.hr[v]);
   }
 }
 
@@ -692,9 +701,13 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 //     Q <- 2Q + D1 Q + Q D1.  Z_k = Q.
 //  5. T_j = Tr(Z_k^dag Hc[j]) in FP64, grad = (2 dt / d^2) Im(conj(g) T_j).
 // Two workgroups per CU (two waves per SIMD) where the LDS allows it, so
-// that one workgroup's LDS and VALU work overlaps the other's MFMAs.
+// that one workgroup's LDS and VALU work overlaps the other's MFMAs.  H_k is
+// loaded together with the W factors where the extra registers cost no
+// occupancy (FP32 at D = 64, FP64 at D = 32).
 template <typename T, int D>
 constexpr int kAdjWaves = (sizeof(T) == 4 && D <= 64) ? 2 : 1;
+template <typename T, int D>
+constexpr bool kEarlyH = (sizeof(T) == 4 && D == 64) || (sizeof(T) == 8 && D == 32);
 
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves<T, D>)))
@@ -713,12 +726,15 @@ void k_adjoint(Work W) {
   const int c = k / P.L;
   Panel<T, D> R1, R2, A1, A2;
 
-  // 1. W = bloc[k] (mc[c] xprev[k]^dag)
+  // 1. W = bloc[k] (mc[c] xprev[k]^dag).  The slice's global loads (mc,
+  //    xprev, bloc and, where the registers allow, H_k) are all issued first.
+  HamRegs<T, D> ham;
+  if constexpr (kEarlyH<T, D>) ham_load<T, D>(ham, pf_mat<T, D>(P.hk, k - W.rg.kbase));
   panel_load(A1, pf_mat<T, D>(P.mc, c), L);
-  Ops::store(lds[0], A1, L);
   panel_load(A2, pf_mat<T, D>(P.xprev, k - W.rg.kbase), L);
-  Ops::store(lds[1], A2, L);
   panel_load(R2, pf_mat<T, D>(P.bloc, k - W.rg.kbase), L);
+  Ops::store(lds[0], A1, L);
+  Ops::store(lds[1], A2, L);
   __syncthreads();
   Ops::load_ct(A2, lds[1], L);
   Ops::gemm3(A1, lds[0], A2, L, true);
@@ -732,8 +748,12 @@ void k_adjoint(Work W) {
   const T scl = (T)ldexp(1.0, -s);
   panel_scale(R2, scl);
   Ops::store(lds[1], R2, L);
-  if constexpr (kKeepH<D>) load_hamiltonian<T, D, Ops>(lds[0], pf_mat<T, D>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
-  else assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
+  if constexpr (kKeepH<D>) {
+    if constexpr (!kEarlyH<T, D>) ham_load<T, D>(ham, pf_mat<T, D>(P.hk, k - W.rg.kbase));
+    ham_put<T, D, Ops>(lds[0], ham, ldexp(P.dt, -s), -1.0);
+  } else {
+    assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
+  }
   __syncthreads();
   const void* X = lds[0];
   const void* E = lds[1];
