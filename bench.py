@@ -34,7 +34,7 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     complex product ("adjoint_8d3").
 
     Complex d x d products per slice: expm q - 1 + s; scans one per
-    direction; adjoint 3 (qb + s) - 2 (two for W, three per block Horner
+    direction; adjoint 3 (qb + s) - 3 (one for W, three per block Horner
     step or squaring, less the top-left blocks the last step does not need).
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
     the three-product (Gauss) form.  FP32 and FP64 use the latter in every
@@ -51,7 +51,7 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     g_adj = G3 if (mid or big32) else G4
     g_expm = G3 if (mid or big32) else G4
     g_scan = G3 if mid else G4
-    n_adj = 3 * (qb + s) - 2
+    n_adj = 3 * (qb + s) - 3
     return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * g_scan * len(s)),
             "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
 

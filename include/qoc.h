@@ -143,8 +143,9 @@ int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const 
  * a pair of hipEvents on its stream around each stage of the path.
  * qoc_stage_times(n, ms, launches) waits for the recorded events, writes for
  * stages 0..n-1 the summed milliseconds and the number of timed launches, and
- * clears the record.  Stages: 0 prep, 1 plan, 2 expm, 3 scan, 4 carry, 5 mc,
- * 6 adjoint (see qoc_stage_name).  Returns QOC_OK or QOC_ERR_DEVICE.
+ * clears the record.  Stages: 0 prep, 1 plan, 2 expm, 3 scan (forward),
+ * 4 carry, 5 mc, 6 bscan (backward scan), 7 adjoint (see qoc_stage_name).
+ * Returns QOC_OK or QOC_ERR_DEVICE.
  */
 int qoc_stage_timing(int enable);
 int qoc_stage_times(int n, double* ms, int64_t* launches);

@@ -82,11 +82,12 @@ qoc_options defaults() {
   return o;
 }
 
-// Stage sequence of the path.  Without checkpointing: prep, plan, expm,
-// scans, carry, then mc and adjoint for the gradient.  With checkpointing the
+// Stage sequence of the path.  Without checkpointing: prep, plan, expm, the
+// forward scans, carry, then for the gradient mc, the backward scans (which
+// start every chunk from its mc) and the adjoint.  With checkpointing the
 // per-slice arrays hold one segment at a time: a first sweep over segments
-// (expm, scans) yields every chunk total, the carry and mc run once, and a
-// second sweep recomputes each segment's propagators and local products
+// (expm, forward scans) yields every chunk total, the carry and mc run once,
+// and a second sweep recomputes each segment's propagators and local products
 // before its adjoint pass.  The recomputation is bitwise identical.
 hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int flags) {
   using namespace qoc;
@@ -105,6 +106,7 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
     run(ST_CARRY, all);
     if (grad) {
       run(ST_MC, all);
+      run(ST_BSCAN, all);
       run(ST_ADJ, all);
     }
     return e;
@@ -127,6 +129,7 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
       const Range rg = segment(c);
       run(ST_EXPM, rg);
       run(ST_SCAN, rg);
+      run(ST_BSCAN, rg);
       run(ST_ADJ, rg);
     }
   }
@@ -347,7 +350,7 @@ int qoc_stage_times(int n, double* ms, int64_t* launches) {
 }
 
 const char* qoc_stage_name(int stage) {
-  static const char* names[] = {"prep", "plan", "expm", "scan", "carry", "mc", "adjoint"};
+  static const char* names[] = {"prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint"};
   return (stage >= 0 && stage < qoc::ST_COUNT) ? names[stage] : "";
 }
 

@@ -35,9 +35,8 @@ struct ProbDesc {
   void* delta;        // N PF matrices: U_k - I
   void* hk;           // N planar matrices: H_k, kept by the expm pass for the adjoint (D >= 32)
   void* xprev;        // N PF matrices: U_{k-1} ... U_{k0}   (I at a chunk start)
-  void* bloc;         // N PF matrices: U_{k+1}^dag ... U_{k1-1}^dag (I at a chunk end)
-  void* tf;           // P PF matrices: forward chunk totals
-  void* tb;           // P PF matrices: backward chunk totals
+  void* bloc;         // N PF matrices: U_{k+1}^dag ... U_{k1-1}^dag mc[c] (mc[c] at a chunk end)
+  void* tf;           // P PF matrices: forward chunk totals (their conjugate transposes are the backward ones)
   void* cf;           // P PF matrices: forward carry into each chunk
   void* cb;           // P PF matrices: backward carry out of each chunk
   void* mc;           // P PF matrices: cb[c] cf[c]^dag
@@ -80,7 +79,7 @@ constexpr int kScratchSlots = 256;
 constexpr int kScratchMats = 6;
 
 // Stages of the path, for the optional per-stage event timing.
-enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_ADJ, ST_COUNT };
+enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_BSCAN, ST_ADJ, ST_COUNT };
 void stage_mark(int stage, bool begin, hipStream_t st);
 
 // Sub-range of a uniform launch: slices [s_lo, s_lo + s_n) and chunks
@@ -130,7 +129,7 @@ struct Layout {
   int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
   int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
-  size_t Hint, Vint, norms, sq, delta, hk, xprev, bloc, tf, tb, cf, cb, mc, small;
+  size_t Hint, Vint, norms, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, small;
   int per_slice;  // per-slice arrays: delta, xprev, bloc, and hk at D >= 32
   size_t per_prob;
   size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
@@ -139,7 +138,7 @@ struct Layout {
 
 // hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
 // batch: the per-slice arrays (three stored propagators, and the slice
-// Hamiltonians at D >= 32) plus the five per-chunk arrays.  When the
+// Hamiltonians at D >= 32) plus the four per-chunk arrays.  When the
 // full arrays do not fit, slices are processed in segments of G chunks whose
 // per-slice arrays are recomputed for the adjoint pass (sqrt(N)
 // checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
@@ -152,9 +151,9 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
   Lo.G = Lo.P;
   Lo.per_slice = Lo.D >= 32 ? 4 : 3;
-  const double full = (double)B * ((double)Lo.per_slice * N + 5.0 * Lo.P) * (double)mat;
+  const double full = (double)B * ((double)Lo.per_slice * N + 4.0 * Lo.P) * (double)mat;
   if (hbm_budget > 0 && full > (double)hbm_budget) {
-    const double avail = (double)hbm_budget / B - 5.0 * Lo.P * (double)mat;
+    const double avail = (double)hbm_budget / B - 4.0 * Lo.P * (double)mat;
     const double per_chunk = (double)Lo.per_slice * Lo.L * (double)mat;
     Lo.G = avail >= per_chunk ? (int)std::min<double>(Lo.P, floor(avail / per_chunk)) : 1;
   }
@@ -169,7 +168,6 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
-  Lo.tb = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.cb = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.mc = o; o = align_up(o + (size_t)Lo.P * mat);
@@ -212,7 +210,6 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.xprev = pb + Lo.xprev;
   P.bloc = pb + Lo.bloc;
   P.tf = pb + Lo.tf;
-  P.tb = pb + Lo.tb;
   P.cf = pb + Lo.cf;
   P.cb = pb + Lo.cb;
   P.mc = pb + Lo.mc;

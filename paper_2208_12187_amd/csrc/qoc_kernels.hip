@@ -574,18 +574,20 @@ __device__ __forceinline__ void reunitarise(const ProbDesc& P, Panel<float, D>& 
 
 // ---------------------------------------------------------------- chunked scans
 
-// One workgroup per (chunk, direction).  Forward (blockIdx.y = 0): running
-// product S = U_k ... U_{k0}; stores xprev[k] = S before slice k and the chunk
-// total.  Backward (blockIdx.y = 1): S = U_k^dag ... U_{k1-1}^dag; stores
-// bloc[k] = S before slice k is applied and the chunk total.  Each step is
-// S <- S + Delta S (or Delta^dag S) with Delta staged in LDS, double-buffered.
+// One workgroup per chunk.  Forward pass (bwd = 0): running product
+// S = U_k ... U_{k0}; stores xprev[k] = S before slice k and the chunk total
+// tf[c].  Backward pass (bwd = 1, after the carry): S starts from
+// mc[c] = cb[c] cf[c]^dag and becomes U_k^dag ... U_{k1-1}^dag mc[c]; stores
+// bloc[k] = S before slice k is applied, so that the adjoint's
+// W_k = bloc[k] xprev[k]^dag takes one product.  (The backward chunk total
+// that the carry needs is tf[c]^dag.)  Each step is S <- S + Delta S (or
+// Delta^dag S) with Delta staged in LDS, double-buffered.
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
-void k_scan_local(Work W) {
+void k_scan_local(Work W, int bwd) {
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
   __shared__ double red[D / 16];
   Lane L;
-  const int bwd = blockIdx.y;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
   int p, c;
@@ -594,7 +596,7 @@ void k_scan_local(Work W) {
   const int k0 = c * P.L;
   const int k1 = min(P.N, k0 + P.L);
   Panel<T, D> S, nxt, acc;
-  panel_identity(S, L);
+  if (bwd) panel_load(S, pf_mat<T, D>(P.mc, c), L); else panel_identity(S, L);
   const int n = k1 - k0;
   int k = bwd ? k1 - 1 : k0;
   panel_load(nxt, pf_mat<T, D>(P.delta, k - W.rg.kbase), L);
@@ -611,11 +613,13 @@ void k_scan_local(Work W) {
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
   }
-  if constexpr (sizeof(T) == 4) {
-    static_assert(2 * Ops::BYTES >= (int)sizeof(double) * Mat<double, D>::LDS_ELEMS, "LDS too small");
-    if (P.reun_tol >= 0) reunitarise<D>(P, S, &lds[0][0], red, L);
+  if (!bwd) {
+    if constexpr (sizeof(T) == 4) {
+      static_assert(2 * Ops::BYTES >= (int)sizeof(double) * Mat<double, D>::LDS_ELEMS, "LDS too small");
+      if (P.reun_tol >= 0) reunitarise<D>(P, S, &lds[0][0], red, L);
+    }
+    panel_store(pf_mat<T, D>(P.tf, c), S, L);
   }
-  panel_store(pf_mat<T, D>(bwd ? P.tb : P.tf, c), S, L);
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
   }
@@ -639,15 +643,15 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   const int nc = P.P;
   if (bwd) panel_load(S, reinterpret_cast<const T*>(P.Vint), L); else panel_identity(S, L);
   int c = bwd ? nc - 1 : 0;
-  panel_load(nxt, pf_mat<T, D>(bwd ? P.tb : P.tf, c), L);
+  panel_load(nxt, pf_mat<T, D>(P.tf, c), L);
   const int steps = bwd ? nc - 1 : nc;
   for (int i = 0; i < nc; ++i) {
     panel_store(pf_mat<T, D>(bwd ? P.cb : P.cf, c), S, L);
     if (i == steps) break;
     T* buf = lds[i & 1];
-    panel_to_lds(buf, nxt, L);
+    if (bwd) panel_to_lds_ct(buf, nxt, L); else panel_to_lds(buf, nxt, L);  // backward: tf[c]^dag
     const int cn = bwd ? c - 1 : c + 1;
-    if (i + 1 < steps) panel_load(nxt, pf_mat<T, D>(bwd ? P.tb : P.tf, cn), L);
+    if (i + 1 < steps) panel_load(nxt, pf_mat<T, D>(P.tf, cn), L);
     __syncthreads();
     cgemm(acc, buf, S, L, true);
     S = acc;
@@ -666,7 +670,8 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   }
 }
 
-// mc[c] = cb[c] cf[c]^dag for every chunk, so that W_k = bloc[k] mc[c] xprev[k]^dag.
+// mc[c] = cb[c] cf[c]^dag for every chunk, the start of its backward scan, so
+// that W_k = (local backward product) mc[c] xprev[k]^dag.
 template <typename T, int D>
 __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 // ---------------------------------------------------------------- adjoint / gradient
 
 // One workgroup per slice.
-//  1. W_k = bloc[k] mc[c] xprev[k]^dag  (two products).
+//  1. W_k = bloc[k] xprev[k]^dag  (one product; bloc[k] carries mc[c]).
 //  2. X = A_k^dag / 2^s in LDS buffer 0, E = W_k / 2^s in buffer 1.
 //  3. Block Horner of degree qb on M = [[X, E], [0, X]] in delta form:
 //     R = [[R1, R2], [0, R1]], R_qb = I + M/qb, R_i = I + M R_{i+1} / i, and
@@ -723,25 +728,20 @@ void k_adjoint(Work W) {
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
-  const int c = k / P.L;
   Panel<T, D> R1, R2, A1, A2;
 
-  // 1. W = bloc[k] (mc[c] xprev[k]^dag).  The slice's global loads (mc,
-  //    xprev, bloc and, where the registers allow, H_k) are all issued first.
+  // 1. W = bloc[k] xprev[k]^dag (bloc carries mc[c]).  The slice's global
+  //    loads (xprev, bloc and, where the registers allow, H_k) are issued
+  //    together.
   HamRegs<T, D> ham;
   if constexpr (kEarlyH<T, D>) ham_load<T, D>(ham, pf_mat<T, D>(P.hk, k - W.rg.kbase));
-  panel_load(A1, pf_mat<T, D>(P.mc, c), L);
   panel_load(A2, pf_mat<T, D>(P.xprev, k - W.rg.kbase), L);
   panel_load(R2, pf_mat<T, D>(P.bloc, k - W.rg.kbase), L);
-  Ops::store(lds[0], A1, L);
+  Ops::store(lds[0], R2, L);
   Ops::store(lds[1], A2, L);
   __syncthreads();
   Ops::load_ct(A2, lds[1], L);
-  Ops::gemm3(A1, lds[0], A2, L, true);
-  __syncthreads();
-  Ops::store(lds[0], R2, L);
-  __syncthreads();
-  Ops::gemm3(R2, lds[0], A1, L, true);  // R2 = W
+  Ops::gemm3(R2, lds[0], A2, L, true);  // R2 = W
   __syncthreads();
 
   // 2. E = W / 2^s, X = A^dag / 2^s
@@ -1245,19 +1245,18 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_scan128(Work W, int dirs) {
+__global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   Lane L;
   const Items I(W);
-  for (int item = blockIdx.x; item < I.total * dirs; item += gridDim.x) {
-    const int bwd = item % dirs;
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, c;
-    split_item(item / dirs, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+    split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     const int k0 = c * P.L;
     const int k1 = min(P.N, k0 + P.L);
     Panel<T, 128> acc;
-    panel_identity(acc, L);
+    if (bwd) panel_load(acc, pf_mat<T, 128>(P.mc, c), L); else panel_identity(acc, L);
     if (!bwd) {
       panel_store(pf_mat<T, 128>(P.xprev, k0 - W.rg.kbase), acc, L);
       for (int k = k0; k < k1; ++k) {
@@ -1272,7 +1271,7 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int dirs) {
         T* cur = pf_mat<T, 128>(P.bloc, k - W.rg.kbase);
         gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.delta, k - W.rg.kbase), cur, L, true);
         panel_axpy_pf(acc, (T)1, cur, L);
-        panel_store(k > k0 ? pf_mat<T, 128>(P.bloc, k - 1 - W.rg.kbase) : pf_mat<T, 128>(P.tb, c), acc, L);
+        if (k > k0) panel_store(pf_mat<T, 128>(P.bloc, k - 1 - W.rg.kbase), acc, L);
       }
     }
     __syncthreads();
@@ -1306,7 +1305,7 @@ __global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratc
       panel_load(acc, reinterpret_cast<const T*>(P.Vint), L);
       panel_store(pf_mat<T, 128>(P.cb, nc - 1), acc, L);
       for (int c = nc - 1; c >= 1; --c) {
-        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.tb, c), pf_mat<T, 128>(P.cb, c), L, true);
+        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cb, c), L, true);  // tf[c]^dag cb[c]
         panel_store(pf_mat<T, 128>(P.cb, c - 1), acc, L);
       }
     }
@@ -1351,13 +1350,10 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
     unpack_sq(gp(P.sq)[k], s, q, qb);
-    const int c = k / P.L;
     Panel<T, 128> acc;
-    // W = bloc[k] (mc[c] xprev[k]^dag)
+    // W = bloc[k] xprev[k]^dag (bloc carries mc[c])
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k - W.rg.kbase), L);
-    gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.mc, c), S0, L, true);
-    panel_store(S1, acc, L);
-    gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S1, L, true);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S0, L, true);
     // E = W / 2^s, R2 = E / qb
     panel_scale(acc, (T)ldexp(1.0, -s));
     panel_store(SE, acc, L);
@@ -1453,10 +1449,12 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
       else hipLaunchKernelGGL((k_expm<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
       break;
     }
-    case ST_SCAN: {
+    case ST_SCAN:
+    case ST_BSCAN: {
       Work w = L.dyn ? dyn : chunk_work(L, rg);
-      if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), dim3(grid_of(L, w.total, 0), dirs), dim3(NT), 0, st, w);
-      else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), dim3(grid_of(L, w.total, 0), dirs), dim3(NT), 0, st, w);
+      const int bwd = stage == ST_BSCAN ? 1 : 0;
+      if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w, bwd);
+      else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w, bwd);
       break;
     }
     case ST_CARRY: {
@@ -1503,9 +1501,10 @@ static void stage_128(int stage, const Launch& L, const Range& rg, double ur) {
       hipLaunchKernelGGL(k_expm128<T>, dim3(grid_of(L, w.total, cap)), dim3(512), 0, st, w, L.scratch);
       break;
     }
-    case ST_SCAN: {
+    case ST_SCAN:
+    case ST_BSCAN: {
       Work w = L.dyn ? dyn : chunk_work(L, rg);
-      hipLaunchKernelGGL(k_scan128<T>, dim3(grid_of(L, w.total * dirs, 0)), dim3(512), 0, st, w, dirs);
+      hipLaunchKernelGGL(k_scan128<T>, dim3(grid_of(L, w.total, 0)), dim3(512), 0, st, w, stage == ST_BSCAN ? 1 : 0);
       break;
     }
     case ST_CARRY: {

@@ -310,7 +310,7 @@ class Runner:
         return out
 
 
-STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "adjoint")
+STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint")
 
 
 class Engine:

@@ -7,11 +7,11 @@ import bench
 
 
 def _products_adjoint(s, qb):
-    # W = bloc (mc xprev^dag): two products; block Horner from degree qb:
-    # three products per step, the last step without the top-left block
-    # unless squarings follow; each squaring three, the last without the
-    # top-left block.
-    n = 2 + 3 * (qb - 2) + 2 + (1 if s > 0 else 0)
+    # W = bloc xprev^dag: one product; block Horner from degree qb: three
+    # products per step, the last step without the top-left block unless
+    # squarings follow; each squaring three, the last without the top-left
+    # block.
+    n = 1 + 3 * (qb - 2) + 2 + (1 if s > 0 else 0)
     for j in range(s):
         n += 2 + (1 if j + 1 < s else 0)
     return n
@@ -31,7 +31,7 @@ def test_three_product_form_is_counted_where_used():
     f32 = bench.slice_flops(plan, d, 12, "fp32")
     f64 = bench.slice_flops(plan, d, 12, "fp64")
     b16 = bench.slice_flops(plan, d, 12, "bf16x3")
-    n_adj = 10 + 13
+    n_adj = 9 + 12
     assert f32["adjoint"] == 6.0 * d ** 3 * n_adj and f64["adjoint"] == 6.0 * d ** 3 * n_adj
     assert b16["adjoint"] == 24.0 * d ** 3 * n_adj and b16["adjoint_8d3"] == 8.0 * d ** 3 * n_adj
     # expm: q - 1 + s products; scans: one per direction; all three-product
