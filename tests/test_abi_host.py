@@ -55,6 +55,9 @@ def test_argument_errors_before_any_launch():
     u[2, 5] = np.inf
     assert _err(qoc.gradient, p.H0, p.Hc, u, p.dt, p.V, "fp64", True) == -3
     assert _err(qoc.gradient, p.H0, p.Hc, p.u, p.dt, p.V, 7) == -6      # unknown precision
+    assert _err(qoc.gradient, p.H0, p.Hc, p.u[:, :0], p.dt, p.V) == -1   # no slices
+    assert _err(qoc.gradient, p.H0, p.Hc[:0], p.u[:0], p.dt, p.V) == -1  # no controls
+    assert _err(qoc.fidelity, p.H0, p.Hc, p.u[:, :0], p.dt, p.V) == -1
     L = qoc.lib()
     assert L.qoc_workspace_size(0, 16, 1, 1, 0, 0, 0) == 0
     assert L.qoc_workspace_size(1, 16, 0, 1, 0, 0, 0) == 0

@@ -85,6 +85,29 @@ def test_engine_rejects_a_request_larger_than_the_pool(gpu_lib):
     eng.close()
 
 
+def test_engine_rejects_empty_and_oversized_requests(gpu_lib):
+    from paper_2208_12187_amd import qoc
+
+    p = make_request(0, 8, 20, trace_seed=3)
+    eng = qoc.Engine("fp32", pool_bytes=64 << 20, host_bytes=1 << 26, max_active=4)
+    for args, code in (((p.H0, p.Hc, p.u[:, :0], p.dt, p.V), -1),          # no slices
+                       ((p.H0, p.Hc[:0], p.u[:0], p.dt, p.V), -1),         # no controls
+                       ((p.H0, p.Hc, p.u, 0.0, p.V), -1),                  # dt <= 0
+                       ((np.eye(129, dtype=complex), np.eye(129, dtype=complex)[None], np.zeros((1, 4)), 0.1,
+                         np.eye(129, dtype=complex)), -6)):                  # d > 128
+        with pytest.raises(qoc.QocError) as e:
+            eng.submit(*args)
+        assert e.value.code == code
+    # the engine still serves a valid request afterwards
+    rid = eng.submit(p.H0, p.Hc, p.u, p.dt, p.V)
+    got = []
+    while not got:
+        eng.step(wait=True)
+        got = eng.poll()
+    assert got[0][0] == rid and 0 <= got[0][1] <= 1
+    eng.close()
+
+
 def test_engine_poisson_replay_reports_latency(gpu_lib):
     from paper_2208_12187_amd import serve
 
