@@ -628,7 +628,9 @@ void k_scan_local(Work W, int bwd) {
 // One workgroup per (problem, direction): serial product over chunk totals.
 // Forward: cf[c] = P_{k0(c)-1}, ending with X_N, its fidelity against V (FP64
 // accumulation) and the unitarity residual |X_N^dag X_N - I|_F.  Backward:
-// cb[c] = Q_{k1(c)-1}, starting from V.
+// cb[c] = Q_{k1(c)-1}, starting from V.  The chains are serial and run as one
+// workgroup per problem and direction, so they take the three-product form
+// at D >= 32 regardless of its registers (each step is on the latency path).
 template <typename T, int D>
 __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   constexpr int NW = Mat<T, D>::NW;
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
     const int cn = bwd ? c - 1 : c + 1;
     if (i + 1 < steps) panel_load(nxt, pf_mat<T, D>(P.tf, cn), L);
     __syncthreads();
-    cgemm(acc, buf, S, L, true);
+    if constexpr (D >= 32) cgemm3m(acc, buf, S, L, true); else cgemm(acc, buf, S, L, true);
     S = acc;
     c = cn;
   }
