@@ -5,7 +5,7 @@
 // footprint (inputs, outputs and the per-problem workspace, about
 // 4 N D^2 c bytes of per-slice arrays at D >= 32) fits the engine's device arena and
 // a descriptor slot is free.  Admitted requests are grouped by padded
-// dimension D; each D bucket owns a stream and a hipGraph of the seven
+// dimension D; each D bucket owns a stream and a hipGraph of the eight
 // persistent stage kernels, captured once, whose item counts, prefix sums
 // and descriptor slots are read from a small device table.  A tick of a
 // bucket uploads that table for every request admitted to the bucket since
