@@ -17,6 +17,8 @@ from .spin import (
     make_config,
     make_batch,
     make_request,
+    make_random,
+    random_hermitian,
     poisson_trace,
     SERVE_DIMS,
     SERVE_WEIGHTS,
@@ -33,6 +35,8 @@ __all__ = [
     "make_config",
     "make_batch",
     "make_request",
+    "make_random",
+    "random_hermitian",
     "poisson_trace",
     "SERVE_DIMS",
     "SERVE_WEIGHTS",

@@ -169,6 +169,25 @@ def make_batch(i: int, B: int, N: Optional[int] = None) -> List[Problem]:
     return [make_config(i, copy=b + 1, N=N) for b in range(B)]
 
 
+def random_hermitian(d: int, rng: np.random.Generator, scale: float = 1.0) -> np.ndarray:
+    """(G + G^dag) / 2 for a complex Ginibre matrix G with unit-variance
+    entries, times scale / sqrt(d) (spectral radius of order scale)."""
+    g = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    return np.ascontiguousarray(scale * (g + g.conj().T) / (2.0 * np.sqrt(d)))
+
+
+def make_random(seed: int, d: int, m: int, N: int, dt: float, u_scale: float = 0.5) -> Problem:
+    """A problem with dense random Hermitian drift and controls of any d (not
+    only powers of two), u ~ N(0, u_scale), Haar target; seeded with
+    SeedSequence([seed, d, m, N]) and drawn in the order H0, Hc, u, V."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, d, m, N]))
+    H0 = random_hermitian(d, rng)
+    Hc = np.stack([random_hermitian(d, rng) for _ in range(m)])
+    u = rng.normal(0.0, u_scale, size=(m, N))
+    V = haar_unitary(d, rng)
+    return Problem(H0, Hc, u, dt, V, f"random{seed}.{d}x{m}x{N}")
+
+
 # Serving workload: request dimensions and their weights.
 SERVE_DIMS = (2, 4, 8, 16, 32, 64, 128)
 SERVE_WEIGHTS = (0.10, 0.15, 0.20, 0.20, 0.15, 0.12, 0.08)
