@@ -33,7 +33,8 @@ struct ProbDesc {
   double* norms;      // m+1 one-norms of H0, Hc[j] (FP64)
   int* sq;            // per slice: s | q << 8 | qb << 16
   void* delta;        // N PF matrices: U_k - I
-  void* hk;           // N planar matrices: H_k, kept by the expm pass for the adjoint (D >= 32)
+  void* hk;           // N matrices kept by the expm pass for the adjoint (D >= 32): planar H_k
+                      // at D <= 64, X = A_k / 2^s in PF layout at D = 128
   void* xprev;        // N PF matrices: U_{k-1} ... U_{k0}   (I at a chunk start)
   void* bloc;         // N PF matrices: U_{k+1}^dag ... U_{k1-1}^dag mc[c] (mc[c] at a chunk end)
   void* tf;           // P PF matrices: forward chunk totals (their conjugate transposes are the backward ones)

@@ -853,6 +853,25 @@ __device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Pr
   }
 }
 
+// Store row block rb of this wavefront's panel of a PF matrix (the layout of
+// pf_rb_load).
+template <typename T>
+__device__ __forceinline__ void pf_rb_store(T* M, const typename Prec<T>::v4& re, const typename Prec<T>::v4& im,
+                                            int w, int rb, int lane) {
+  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);
+  const int off = pf_index<T, 128>(w, 0, 4 * rb, lane);
+  if constexpr (sizeof(T) == 4) {
+    *(QOC_GLOBAL f4*)(M + off) = re;
+    *(QOC_GLOBAL f4*)(M + off + PLANE) = im;
+  } else {
+    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);
+    *(QOC_GLOBAL d2*)(M + off) = d2{re.x, re.y};
+    *(QOC_GLOBAL d2*)(M + off + R2) = d2{re.z, re.w};
+    *(QOC_GLOBAL d2*)(M + off + PLANE) = d2{im.x, im.y};
+    *(QOC_GLOBAL d2*)(M + off + PLANE + R2) = d2{im.z, im.w};
+  }
+}
+
 // acc <- acc + a * (this wavefront's panel of the PF matrix M), one row block
 // at a time so that no second panel is held in registers.
 template <typename T>
@@ -1015,36 +1034,27 @@ __device__ __forceinline__ void transpose128(T* out, T* lds, const T* M, const L
   }
 }
 
-// Write the chunk (row, col..col+3) of sgn * (-i) * c * (hr + i hi) into the
-// PF matrix out.
+// X <- sgn * (-i) * c * H_k (this wavefront's panel, in registers) with
+// H_k = H0 + sum_j u_jk Hc[j].  The matrix is read as chunks of four
+// consecutive row elements, chunk t + 512 i by thread t, so that every
+// 16-byte load is consecutive across lanes and a control's loads are all in
+// flight together; the chunks then go through LDS (row-major, the layout of
+// the staged left factors) to the panels, which are also stored to the PF
+// matrix out.  FP32 takes all rows at once, FP64 one half of the rows per
+// pass (one FP64 matrix does not fit in LDS); FP64 writes each half's rows of
+// the panel to out and reads the panel back at the end, so that no panel is
+// held across the passes.  Starts and ends with a workgroup barrier.
 template <typename T>
-__device__ __forceinline__ void put4_pf128(T* out, int e, T f, const typename Prec<T>::v4& hr,
-                                           const typename Prec<T>::v4& hi) {
-  constexpr int D = 128;
-  const int row = e / D, col = e % D;
-  const int rb = row >> 4, rr = row & 15;
-  int r, g;
-  if (sizeof(T) == 4) { g = rr >> 2; r = rr & 3; } else { r = rr >> 2; g = rr & 3; }
-  const int reg = 4 * rb + r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int w = (col + i) >> 4, lane = 16 * g + ((col + i) & 15);
-    out[pf_index<T, D>(w, 0, reg, lane)] = f * hi[i];
-    out[pf_index<T, D>(w, 1, reg, lane)] = -f * hr[i];
-  }
-}
-
-// out (PF) <- sgn * (-i) * c * H_k with H_k = H0 + sum_j u_jk Hc[j]; when hk
-// is not null, H_k itself is also written there (planar, row-major).  The
-// matrix is read as chunks of four consecutive row elements, chunk t + 512 i
-// by thread t, so that every 16-byte load is consecutive across lanes and a
-// control's loads are all in flight together (FP64: half the chunks per pass).
-template <typename T>
-__device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, double c, double sgn, T* hk) {
+__device__ __forceinline__ void assemble128(Panel<T, 128>& X, T* out, T* lds, const ProbDesc& P, int k, double c,
+                                            double sgn, const Lane& L) {
   using v4 = typename Prec<T>::v4;
   constexpr int D = 128, NT = 512;
   constexpr int PASSES = sizeof(T) == 4 ? 1 : 2;
   constexpr int NV = D * D / 4 / NT / PASSES;
+  constexpr int ROWS = D / PASSES;
+  constexpr int SD = D + Prec<T>::PAD;
+  static_assert(2 * ROWS * SD <= K128<T>::LDS_ELEMS, "LDS too small");
+  T* lim = lds + ROWS * SD;
   const T* H = reinterpret_cast<const T*>(P.Hint);
   const T f = (T)(sgn * c);
 #pragma unroll
@@ -1071,38 +1081,40 @@ __device__ __forceinline__ void assemble128(T* out, const ProbDesc& P, int k, do
         hi[v] += uj * ai[v];
       }
     }
+    __syncthreads();  // LDS free
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const int e = e0 + 4 * NT * v;
-      if (hk) {
-        Prec<T>::gst4(hk + e, hr[v]);
-        Prec<T>::gst4(hk + D * D + e, hi[v]);
+      const int row = e / D - pass * ROWS, col = e % D;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int off = row * SD + ((col + i) & ~15) + Prec<T>::perm((col + i) & 15);
+        lds[off] = f * hi[v][i];   // -i f (hr + i hi)
+        lim[off] = -f * hr[v][i];
       }
-      put4_pf128<T>(out, e, f, hr[v], hi[v]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8 / PASSES; ++i) {
+      const int rb = pass * (8 / PASSES) + i;
+      v4 re, im;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int off = (16 * i + Prec<T>::rowmap(r, L.g)) * SD + 16 * L.w + Prec<T>::perm(L.c16);
+        re[r] = lds[off];
+        im[r] = lim[off];
+      }
+      if constexpr (PASSES == 1) {
+        X.re[rb] = re;
+        X.im[rb] = im;
+      } else {
+        pf_rb_store<T>(out, re, im, L.w, rb, L.lane);
+      }
     }
   }
-}
-
-// out (PF) <- sgn * (-i) * c * H_k from the planar H_k that k_expm128 stored.
-template <typename T>
-__device__ __forceinline__ void load_hamiltonian128(T* out, const T* hk, double c, double sgn) {
-  using v4 = typename Prec<T>::v4;
-  constexpr int D = 128, NT = 512;
-  constexpr int PASSES = sizeof(T) == 4 ? 1 : 2;
-  constexpr int NV = D * D / 4 / NT / PASSES;
-  const T f = (T)(sgn * c);
-#pragma unroll
-  for (int pass = 0; pass < PASSES; ++pass) {
-    const int e0 = 4 * (threadIdx.x + pass * NV * NT);
-    v4 hr[NV], hi[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      hr[v] = Prec<T>::gld4(hk + e0 + 4 * NT * v);
-      hi[v] = Prec<T>::gld4(hk + D * D + e0 + 4 * NT * v);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) put4_pf128<T>(out, e0 + 4 * NT * v, f, hr[v], hi[v]);
-  }
+  if constexpr (PASSES == 1) panel_store(out, X, L);
+  else panel_load(X, out, L);  // own panel
+  __syncthreads();
 }
 
 // The gradient epilogue at D = 128 (512 threads), as gradient_epilogue: Z goes
@@ -1219,12 +1231,11 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
     int s, q, qb;
     unpack_sq(gp(P.sq)[k], s, q, qb);
-    __syncthreads();
-    T* hk = (P.flags & RUN_GRAD) ? pf_mat<T, 128>(P.hk, k - W.rg.kbase) : nullptr;
-    assemble128<T>(SX, P, k, ldexp(P.dt, -s), 1.0, hk);
-    __syncthreads();
     Panel<T, 128> acc;
-    panel_load(acc, SX, L);
+    assemble128<T>(acc, SX, lds, P, k, ldexp(P.dt, -s), 1.0, L);  // SX: the left factor of the products
+    // For the adjoint: X = A_k / 2^s in PF layout (its X, A_k^dag / 2^s, is
+    // the exact negation), one coalesced store of this wavefront's panel.
+    if (P.flags & RUN_GRAD) panel_store(pf_mat<T, 128>(P.hk, k - W.rg.kbase), acc, L);
     if (q >= 2) {
       panel_scale(acc, (T)(1.0 / q));
       panel_add_identity(acc, L, (T)1);
@@ -1361,11 +1372,12 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     panel_store(SE, acc, L);
     panel_scale(acc, (T)(1.0 / qb));
     panel_store(SR2, acc, L);
-    // X = A^dag / 2^s, R1 = I + X / qb
-    __syncthreads();
-    load_hamiltonian128<T>(SX, pf_mat<T, 128>(P.hk, k - W.rg.kbase), ldexp(P.dt, -s), -1.0);
-    __syncthreads();
-    panel_load(acc, SX, L);
+    // X = A^dag / 2^s = -(A / 2^s), the expm pass's matrix negated (own
+    // panel; the barrier at the start of the next product publishes SX)
+    panel_load(acc, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
+    panel_scale(acc, (T)-1);
+    panel_store(SX, acc, L);
+    // R1 = I + X / qb
     panel_scale(acc, (T)(1.0 / qb));
     panel_add_identity(acc, L, (T)1);
     panel_store(SR1, acc, L);
