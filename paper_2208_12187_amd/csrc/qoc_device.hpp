@@ -373,9 +373,64 @@ __host__ __device__ constexpr int pf_index(int w, int plane, int reg, int lane) 
   return ((w * 2 + plane) * (D / 4 / G) + reg / G) * 64 * G + lane * G + reg % G;
 }
 
+// Offset of one row block of a d = 128 PF panel access.  It passes through an
+// empty asm statement, so that each access's address is formed where the
+// access is issued: otherwise the compiler precomputes the 64-bit addresses
+// of all sixteen row blocks of a product, spills them, and every reload waits
+// for all outstanding memory operations.
+__device__ __forceinline__ int pf_site_offset(int off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+
+// Row block rb of this wavefront's panel of a PF matrix, addressed at the
+// access site (pf_site_offset).
+template <typename T>
+__device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Prec<T>::v4& im, const T* M, int w,
+                                           int rb, int lane) {
+  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);  // offset of the imaginary plane
+  const int off = pf_site_offset(pf_index<T, 128>(w, 0, 4 * rb, lane));
+  if constexpr (sizeof(T) == 4) {
+    re = *(const QOC_GLOBAL f4*)(M + off);
+    im = *(const QOC_GLOBAL f4*)(M + off + PLANE);
+  } else {
+    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);  // offset of registers 2 and 3
+#pragma unroll
+    for (int plane = 0; plane < 2; ++plane) {
+      d2 a = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE);
+      d2 b = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE + R2);
+      d4 v;
+      v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
+      if (plane == 0) re = v; else im = v;
+    }
+  }
+}
+
+// Store row block rb of this wavefront's panel of a PF matrix (the layout of
+// pf_rb_load).
+template <typename T>
+__device__ __forceinline__ void pf_rb_store(T* M, const typename Prec<T>::v4& re, const typename Prec<T>::v4& im,
+                                            int w, int rb, int lane) {
+  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);
+  const int off = pf_site_offset(pf_index<T, 128>(w, 0, 4 * rb, lane));
+  if constexpr (sizeof(T) == 4) {
+    *(QOC_GLOBAL f4*)(M + off) = re;
+    *(QOC_GLOBAL f4*)(M + off + PLANE) = im;
+  } else {
+    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);
+    *(QOC_GLOBAL d2*)(M + off) = d2{re.x, re.y};
+    *(QOC_GLOBAL d2*)(M + off + R2) = d2{re.z, re.w};
+    *(QOC_GLOBAL d2*)(M + off + PLANE) = d2{im.x, im.y};
+    *(QOC_GLOBAL d2*)(M + off + PLANE + R2) = d2{im.z, im.w};
+  }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void panel_load(Panel<T, D>& P, const T* M, const Lane& L) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (D == 128) {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) pf_rb_load<T>(P.re[rb], P.im[rb], M, L.w, rb, L.lane);
+  } else if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
       P.re[rb] = *(const QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane));
@@ -398,7 +453,10 @@ __device__ __forceinline__ void panel_load(Panel<T, D>& P, const T* M, const Lan
 
 template <typename T, int D>
 __device__ __forceinline__ void panel_store(T* M, const Panel<T, D>& P, const Lane& L) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (D == 128) {
+#pragma unroll
+    for (int rb = 0; rb < D / 16; ++rb) pf_rb_store<T>(M, P.re[rb], P.im[rb], L.w, rb, L.lane);
+  } else if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int rb = 0; rb < D / 16; ++rb) {
       *(QOC_GLOBAL f4*)(M + pf_index<T, D>(L.w, 0, 4 * rb, L.lane)) = P.re[rb];

@@ -826,52 +826,6 @@ struct K128 {
   static constexpr int WPH = NW / HALVES;           // panels per staged part
 };
 
-// Row block rb of this wavefront's panel of a PF matrix.  The element offset
-// passes through an empty asm statement, so that each load's address is
-// formed where the load is issued: otherwise the compiler precomputes the
-// 64-bit addresses of every row block of a product and spills them, and each
-// reload waits for all outstanding loads.
-template <typename T>
-__device__ __forceinline__ void pf_rb_load(typename Prec<T>::v4& re, typename Prec<T>::v4& im, const T* M, int w,
-                                           int rb, int lane) {
-  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);  // offset of the imaginary plane
-  int off = pf_index<T, 128>(w, 0, 4 * rb, lane);
-  asm volatile("" : "+v"(off));
-  if constexpr (sizeof(T) == 4) {
-    re = *(const QOC_GLOBAL f4*)(M + off);
-    im = *(const QOC_GLOBAL f4*)(M + off + PLANE);
-  } else {
-    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);  // offset of registers 2 and 3
-#pragma unroll
-    for (int plane = 0; plane < 2; ++plane) {
-      d2 a = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE);
-      d2 b = *(const QOC_GLOBAL d2*)(M + off + plane * PLANE + R2);
-      d4 v;
-      v.x = a.x; v.y = a.y; v.z = b.x; v.w = b.y;
-      if (plane == 0) re = v; else im = v;
-    }
-  }
-}
-
-// Store row block rb of this wavefront's panel of a PF matrix (the layout of
-// pf_rb_load).
-template <typename T>
-__device__ __forceinline__ void pf_rb_store(T* M, const typename Prec<T>::v4& re, const typename Prec<T>::v4& im,
-                                            int w, int rb, int lane) {
-  constexpr int PLANE = pf_index<T, 128>(0, 1, 0, 0);
-  const int off = pf_index<T, 128>(w, 0, 4 * rb, lane);
-  if constexpr (sizeof(T) == 4) {
-    *(QOC_GLOBAL f4*)(M + off) = re;
-    *(QOC_GLOBAL f4*)(M + off + PLANE) = im;
-  } else {
-    constexpr int R2 = pf_index<T, 128>(0, 0, 2, 0);
-    *(QOC_GLOBAL d2*)(M + off) = d2{re.x, re.y};
-    *(QOC_GLOBAL d2*)(M + off + R2) = d2{re.z, re.w};
-    *(QOC_GLOBAL d2*)(M + off + PLANE) = d2{im.x, im.y};
-    *(QOC_GLOBAL d2*)(M + off + PLANE + R2) = d2{im.z, im.w};
-  }
-}
-
 // acc <- acc + a * (this wavefront's panel of the PF matrix M), one row block
 // at a time so that no second panel is held in registers.
 template <typename T>
