@@ -65,20 +65,23 @@ def time_runner(qoc, torch, runner, batch, steps, warmup):
     qoc.stage_times()
     qoc.stage_timing(True)
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         runner.gradient(batch, F, grad)
-    e1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     qoc.stage_timing(False)
     stages = qoc.stage_times()
-    ms = e0.elapsed_time(e1) / steps
-    return {"ms_per_step": ms, "wall_s": wall, "stages": stages, "F": F.cpu().numpy(), "grad": grad}
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    lat = {"p50_ms": round(float(np.percentile(per, 50)), 4), "p99_ms": round(float(np.percentile(per, 99)), 4),
+           "mean_ms": round(float(per.mean()), 4)}
+    return {"ms_per_step": ms, "wall_s": wall, "stages": stages, "F": F.cpu().numpy(), "grad": grad,
+            "latency": lat}
 
 
 def measured_traffic(kernel_avg_ms):
@@ -101,22 +104,28 @@ def measured_traffic(kernel_avg_ms):
 
 
 def cpu_baseline():
-    """The CPU oracle on one full configuration-3 problem (N = 2000 slices)."""
+    """The CPU oracle on one full configuration-3 problem (N = 2000 slices,
+    the first problem of the benchmark batch), with the BLAS thread pools at
+    their default size and again at one thread.  Returns (baseline, one-thread
+    baseline, oracle result)."""
     import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
     from workloads import make_config
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     p = make_config(CFG, copy=1)
     t0 = time.perf_counter()
-    oracle.grape_ref(p)
+    ref = oracle.grape_ref(p)
     dt = time.perf_counter() - t0
-    return {"value": p.N / dt, "unit": "slice-steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one configuration-3 problem (d=64, m=12, N={p.N}) fwd+grad, {dt:.1f} s",
-            "seconds": dt}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.grape_ref(p)
+        dt1 = time.perf_counter() - t0
+    sample = f"one configuration-3 problem (d=64, m=12, N={p.N}) fwd+grad"
+    return ({"value": p.N / dt, "unit": "slice-steps/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"{sample}, {dt:.1f} s"},
+            {"value": round(p.N / dt1, 2), "unit": "slice-steps/s", "cores": 1, "kind": "oracle",
+             "sample": f"{sample}, {dt1:.1f} s"}, ref)
 
 
 def main():
@@ -219,7 +228,14 @@ def main():
         b1 = qoc.Batch(batch.H0[:1], batch.Hc[:1], batch.u[:1], batch.dt, batch.V[:1])
         one = leg(args.precision, args.steps, 1, b1)
         extra["batch1"] = {"value": round(N / (one["ms_per_step"] / 1e3), 1),
-                           "ms_per_step": round(one["ms_per_step"], 3)}
+                           "ms_per_step": round(one["ms_per_step"], 3), "latency": one["latency"]}
+        for pr in ("fp64", "bf16x3"):
+            if pr == args.precision or (pr == "fp64" and args.no_fp64) or \
+                    (pr == "bf16x3" and (args.no_bf16 or not 16 < d <= 64)):
+                continue
+            o = leg(pr, args.steps, 1, b1)
+            extra["batch1"][pr] = {"value": round(N / (o["ms_per_step"] / 1e3), 1),
+                                   "ms_per_step": round(o["ms_per_step"], 3), "latency": o["latency"]}
         # the host-pointer entry point on the same problem: device allocation,
         # host-to-device copies, the path and the copy back, per call
         p0 = problems[0]
@@ -233,7 +249,14 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline()
+        cpu, cpu1, ref = cpu_baseline()
+        extra["cpu_baseline_1thread"] = cpu1
+        if args.config == CFG:
+            # the headline run's first problem is the oracle's sample
+            g0 = head["grad"][0].cpu().numpy()
+            extra["vs_oracle_problem0"] = {"abs_dF": float(abs(head["F"][0] - ref["F"])),
+                                           "grad_err_rel_max": float(np.max(np.abs(g0 - ref["grad"]))
+                                                                     / np.max(np.abs(ref["grad"])))}
 
     out = {
         "metric": METRIC,
@@ -253,8 +276,9 @@ def main():
                    "d": d, "m": m, "N": N, "batch": B, "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": None if cpu is None else {k: (round(v, 2) if isinstance(v, float) else v)
-                                                  for k, v in cpu.items() if k != "seconds"},
+                                                  for k, v in cpu.items()},
         "path_tflops": round(total_flops / (ms / 1e3) / 1e12, 2),
+        "latency": head["latency"],
         "stages_ms": stages,
     }
     out.update(extra)

@@ -21,7 +21,7 @@ from .autograd import GrapeProblem, fidelity
 
 
 def optimise(problem: GrapeProblem, u0: torch.Tensor, iters: int = 50, method: str = "lbfgs",
-             lr: float = 1.0, checkpoint: str | None = None, scale: float | None = None):
+             lr: float = 1.0, checkpoint: str | None = None, scale: float | None = None, max_ls: int = 25):
     """Run `iters` optimiser iterations from u0 [B, m, N]; returns (u, history).
 
     The optimiser works on x = u / scale.  Each amplitude only enters through
@@ -29,6 +29,9 @@ def optimise(problem: GrapeProblem, u0: torch.Tensor, iters: int = 50, method: s
     (length 1 / |g|_1 in the gradient direction) barely moves u; with the
     default scale = 0.75 sqrt(m N) that first step changes each amplitude by
     about 0.75 / sqrt(m N).
+
+    Each L-BFGS iteration runs a strong-Wolfe line search of at most max_ls
+    objective evaluations.
 
     history: list of dicts {iter, F (list over the batch), evals, seconds};
     entry 0 is the starting point."""
@@ -50,7 +53,13 @@ def optimise(problem: GrapeProblem, u0: torch.Tensor, iters: int = 50, method: s
         return -fidelity(x * scale, problem).sum()
 
     if method == "lbfgs":
-        opt = torch.optim.LBFGS([x], lr=lr, max_iter=1, history_size=20, line_search_fn="strong_wolfe")
+        # One L-BFGS iteration per step() call.  torch gives the line search
+        # max_eval minus the evaluations already made in the call, and the
+        # default max_eval (5/4 of max_iter) would leave it none: a trial step
+        # that does not lower the objective would then be replaced by a zero
+        # step, and every later call would retry the same rejected direction.
+        opt = torch.optim.LBFGS([x], lr=lr, max_iter=1, max_eval=1 + max_ls, history_size=20,
+                                line_search_fn="strong_wolfe")
 
         def closure():
             opt.zero_grad()

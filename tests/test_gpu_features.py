@@ -80,8 +80,9 @@ def test_lbfgs_raises_fidelity(gpu_lib):
 
 def test_differentiation_workload_full_size(gpu_lib):
     """d = 128, m = 14, N = 1000, FP64 with checkpointing forced by a 64 MB
-    budget: F and the full gradient against the oracle, and central finite
-    differences (h = 1e-6) of the GPU FP64 fidelity on 32 random entries."""
+    budget: F and the full gradient against the oracle and bitwise equal to
+    the run without a budget, and central finite differences (h = 1e-6) of
+    the GPU FP64 fidelity on 32 random entries."""
     from paper_2208_12187_amd import qoc
 
     p = make_config(4)
@@ -92,6 +93,9 @@ def test_differentiation_workload_full_size(gpu_lib):
     assert abs(F - ref["F"]) <= 1e-10 * ref["F"]
     gmax = np.max(np.abs(ref["grad"]))
     assert np.max(np.abs(grad - ref["grad"])) <= 1e-10 * gmax
+    # the forced checkpointing changes where propagators come from, not what they are
+    F_full, grad_full = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp64")
+    assert F_full == F and np.array_equal(grad_full, grad)
     F32, grad32 = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", hbm_budget=budget)
     print(f"[features] config 4 fp32 |dF| = {abs(F32 - ref['F']):.2e}, "
           f"grad err = {np.max(np.abs(grad32 - ref['grad'])) / gmax:.2e}", flush=True)
