@@ -114,18 +114,29 @@ def cpu_baseline():
 
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     p = make_config(CFG, copy=1)
-    t0 = time.perf_counter()
-    ref = oracle.grape_ref(p)
-    dt = time.perf_counter() - t0
+
+    def median3():
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = oracle.grape_ref(p)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
+    dt, ref = median3()
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        oracle.grape_ref(p)
-        dt1 = time.perf_counter() - t0
-    sample = f"one configuration-3 problem (d=64, m=12, N={p.N}) fwd+grad"
+        dt1, _ = median3()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    sample = f"one configuration-3 problem (d=64, m=12, N={p.N}) fwd+grad, median of 3"
     return ({"value": p.N / dt, "unit": "slice-steps/s", "cores": int(threads), "kind": "oracle",
-             "sample": f"{sample}, {dt:.1f} s"},
+             "sample": f"{sample}: {dt:.2f} s", "cpu": model},
             {"value": round(p.N / dt1, 2), "unit": "slice-steps/s", "cores": 1, "kind": "oracle",
-             "sample": f"{sample}, {dt1:.1f} s"}, ref)
+             "sample": f"{sample}: {dt1:.2f} s", "cpu": model}, ref)
 
 
 def main():

@@ -4,7 +4,13 @@
     python -m paper_2208_12187_amd.profile_summary bytes <fetch counter_collection.csv> \
         <write counter_collection.csv> <copy GiB> [<counters json to write>]
 
+    python -m paper_2208_12187_amd.profile_summary mfma <counter_collection.csv>
+
 ``trace`` prints the per-kernel table of a ``--kernel-trace --stats`` run.
+``mfma`` reads a run with the derived counters MfmaUtil (MFMA-busy cycles
+over GPU-active cycles times the SIMD count, in percent) and MfmaFlopsF32 /
+MfmaFlopsF64 / MfmaFlopsBF16 (512 times the MFMA operation counts) and prints
+their per-dispatch means for every kernel.
 ``bytes`` reads one FETCH_SIZE pass and one WRITE_SIZE pass of the same
 command, calibrates each counter against the plain device-to-device copy of
 ``copy GiB`` that the bench makes before timing (``--copy-gib``; the copy
@@ -88,10 +94,24 @@ def bytes_table(fetch_csv: str, write_csv: str, copy_gib: float, json_out: str |
     return "\n".join(lines)
 
 
+def mfma_table(path: str) -> str:
+    names = ("MfmaUtil", "MfmaFlopsF32", "MfmaFlopsF64", "MfmaFlopsBF16")
+    vals = {n: per_kernel(path, n) for n in names}
+    kernels = [k for k in vals["MfmaUtil"] if k.startswith("qoc::")]
+    out = ["| kernel | dispatches | MFMA busy % | MFMA GFLOP per dispatch (F32 / F64 / BF16) |", "|---|---|---|---|"]
+    for k in kernels:
+        u = vals["MfmaUtil"][k]
+        fl = [sum(vals[n].get(k, [0.0])) / max(len(vals[n].get(k, [])), 1) / 1e9 for n in names[1:]]
+        out.append(f"| `{k}` | {len(u)} | {sum(u) / len(u):.1f} | {fl[0]:.2f} / {fl[1]:.2f} / {fl[2]:.2f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     a = sys.argv[1:] if argv is None else argv
     if a and a[0] == "trace" and len(a) == 2:
         print(trace_table(a[1]))
+    elif a and a[0] == "mfma" and len(a) == 2:
+        print(mfma_table(a[1]))
     elif a and a[0] == "bytes" and len(a) in (4, 5):
         print(bytes_table(a[1], a[2], float(a[3]), a[4] if len(a) == 5 else None))
     else:
