@@ -152,6 +152,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
+    ap.add_argument("--no-dense", action="store_true", help="skip the leg with the dense control kernels forced")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="before timing, run one plain device-to-device copy of this many GiB "
                          "(a reference of known size for hardware byte counters)")
@@ -182,8 +183,8 @@ def main():
              for pr in ("fp32", "fp64", "bf16x3")}
     flops = {pr: slice_flops(plans[pr], d, m, pr) for pr in plans}
 
-    def leg(prec, steps, bsz=B, bat=batch):
-        r = qoc.Runner(bsz, d, m, N, prec)
+    def leg(prec, steps, bsz=B, bat=batch, dense_controls=False):
+        r = qoc.Runner(bsz, d, m, N, prec, dense_controls=dense_controls)
         out = time_runner(qoc, torch, r, bat, steps, args.warmup)
         del r
         torch.cuda.empty_cache()
@@ -213,6 +214,19 @@ def main():
     stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in head["stages"].items() if v[1]}
 
     extra = {}
+    if not args.no_dense:
+        # the same workload with the dense control kernels forced (the spin-chain
+        # controls are Pauli strings, which the default path takes row by row)
+        dn = leg(args.precision, args.steps, dense_controls=True)
+        adn_ms, adn_n = dn["stages"]["adjoint"]
+        extra["dense_controls"] = {"value": round(B * N / (dn["ms_per_step"] / 1e3), 1),
+                                   "ms_per_step": round(dn["ms_per_step"], 3),
+                                   "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in dn["stages"].items()
+                                                 if v[1]},
+                                   "adjoint_frac": round(adj_flops / (adn_ms / max(adn_n, 1) / 1e3) / 1e12 / peak, 4),
+                                   "max_abs_dF": float(np.max(np.abs(dn["F"] - head["F"]))),
+                                   "grad_err_rel": float((dn["grad"] - head["grad"]).abs().max().item()
+                                                         / head["grad"].abs().max().item())}
     if not args.no_fp64 and args.precision != "fp64":
         f64 = leg("fp64", max(2, args.steps // 4))
         v64 = B * N / (f64["ms_per_step"] / 1e3)

@@ -166,7 +166,8 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   const double tol = reun_tol(opt);
   for (int b = 0; b < B; ++b) {
     char* pb = base + Lo.desc_bytes + (size_t)b * Lo.per_prob;
-    fill_desc(descs[b], Lo, pb, d, m, N, dt, flags, static_cast<const double*>(H0) + 2 * dd * b,
+    fill_desc(descs[b], Lo, pb, d, m, N, dt, flags | (opt.dense_controls ? qoc::CTRL_DENSE : 0),
+              static_cast<const double*>(H0) + 2 * dd * b,
               static_cast<const double*>(Hc) + 2 * dd * m * b, static_cast<const double*>(u) + (size_t)m * N * b,
               V ? static_cast<const double*>(V) + 2 * dd * b : nullptr, F ? static_cast<double*>(F) + b : nullptr,
               grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr,
@@ -365,6 +366,7 @@ void qoc_default_options(qoc_options* opt) {
   opt->diagnostics = nullptr;
   opt->stream = nullptr;
   opt->chunk = 0;
+  opt->dense_controls = 0;
 }
 
 int qoc_propagate(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,

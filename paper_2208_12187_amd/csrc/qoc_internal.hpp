@@ -31,6 +31,9 @@ struct ProbDesc {
   void* Hint;         // (m+1) planar matrices: [0] = H0, [1 + j] = Hc[j]
   void* Vint;         // PF matrix: V
   double* norms;      // m+1 one-norms of H0, Hc[j] (FP64)
+  int* mcol;          // m*D: column of the nonzero of row a of Hc[j] (a if the row is empty)
+  void* mval;         // m*D complex values (re, im) of those entries, in precision T
+  int* mok;           // m flags: Hc[j] has at most one nonzero per row (and D <= 64)
   int* sq;            // per slice: s | q << 8 | qb << 16
   void* delta;        // N PF matrices: U_k - I
   void* hk;           // N matrices kept by the expm pass for the adjoint (D >= 32): planar H_k
@@ -51,6 +54,7 @@ enum : int {
   RUN_BWD = 1,   // backward scans (needed for the gradient)
   RUN_GRAD = 2,  // adjoint pass and gradient
   RUN_FID = 4,   // fidelity against V
+  CTRL_DENSE = 8,  // always the dense control kernels (qoc_options.dense_controls)
 };
 
 // A launch over many problems that share d (and hence D) and the precision.
@@ -127,10 +131,11 @@ inline size_t elem_size(int precision) { return precision == 0 ? 8 : 4; }
 // Byte offsets of one problem's workspace regions, and the total size.
 struct Layout {
   int D, L, P;
+  int esize;  // bytes of one real element of the compute precision
   int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
   int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
-  size_t Hint, Vint, norms, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, small;
+  size_t Hint, Vint, norms, mono, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, small;
   int per_slice;  // per-slice arrays: delta, xprev, bloc, and hk at D >= 32
   size_t per_prob;
   size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
@@ -146,6 +151,7 @@ struct Layout {
 inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
   Layout Lo;
   Lo.D = padded_dim(d);
+  Lo.esize = (int)elem_size(precision);
   Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
   if (Lo.L < 1) Lo.L = 1;
   Lo.P = (N + Lo.L - 1) / Lo.L;
@@ -163,6 +169,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
   Lo.Vint = o; o = align_up(o + mat);
   Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
+  Lo.mono = o; o = align_up(o + (size_t)m * Lo.D * (4 + 2 * elem_size(precision)) + (size_t)m * 4);
   Lo.sq = o; o = align_up(o + (size_t)N * 4);
   Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.hk = o; o = align_up(o + (Lo.per_slice == 4 ? (size_t)Lo.W * mat : 0));
@@ -205,6 +212,9 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.Hint = pb + Lo.Hint;
   P.Vint = V ? pb + Lo.Vint : nullptr;
   P.norms = reinterpret_cast<double*>(pb + Lo.norms);
+  P.mval = pb + Lo.mono;
+  P.mcol = reinterpret_cast<int*>(pb + Lo.mono + (size_t)m * Lo.D * 2 * Lo.esize);
+  P.mok = P.mcol + (size_t)m * Lo.D;
   P.sq = reinterpret_cast<int*>(pb + Lo.sq);
   P.delta = pb + Lo.delta;
   P.hk = Lo.per_slice == 4 ? pb + Lo.hk : nullptr;

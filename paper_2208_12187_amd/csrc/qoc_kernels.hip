@@ -78,6 +78,55 @@ __device__ __forceinline__ T* pf_mat(void* base, int i) {
 
 // ---------------------------------------------------------------- prep
 
+// Row table of control j (D <= 64): for each row a, the column and value (in
+// precision T, as the dense copy holds it) of its nonzero, and whether every
+// row has at most one.  Such controls (Pauli strings, for instance) are then
+// assembled and paired with Z_k entry by entry.  The table is written even
+// when the control does not qualify; mok[j] says whether it may be used.
+template <typename T, int D>
+__device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const double* src) {
+  const int d = P.d;
+  const int a = threadIdx.x;
+  int multi = 0;
+  if constexpr (D <= 64) {
+    if (a < D) {
+      int col = a, cnt = 0;
+      T vr = 0, vi = 0;
+      if (a < d)
+        for (int c = 0; c < d; ++c) {
+          const T r = (T)src[2 * (a * d + c)], i = (T)src[2 * (a * d + c) + 1];
+          if (r != (T)0 || i != (T)0) {
+            ++cnt;
+            col = c;
+            vr = r;
+            vi = i;
+          }
+        }
+      multi = cnt > 1;
+      const size_t idx = (size_t)j * D + a;
+      gp(P.mcol)[idx] = col;
+      gp(reinterpret_cast<T*>(P.mval))[2 * idx] = vr;
+      gp(reinterpret_cast<T*>(P.mval))[2 * idx + 1] = vi;
+    }
+  }
+  const int any = __syncthreads_or(multi);
+  if (threadIdx.x == 0) gp(P.mok)[j] = (D <= 64 && !any && !(P.flags & CTRL_DENSE)) ? 1 : 0;
+}
+
+// True when every control of the problem has a usable row table (D <= 64,
+// at most one nonzero per row, dense kernels not forced).  Uniform across
+// the workgroup.
+template <int D>
+__device__ __forceinline__ bool controls_monomial(const ProbDesc& P) {
+  if constexpr (D > 64) {
+    return false;
+  } else {
+    for (int j = 0; j < P.m; ++j)
+      if (!gp(P.mok)[j]) return false;
+    return true;
+  }
+}
+
 // Convert the caller's complex128 matrices to the compute precision: H0 and
 // Hc[j] to planar D x D (zero padded), V to PF; also the FP64 one-norms
 // (largest column sum of moduli) of H0 and Hc[j].
@@ -114,6 +163,7 @@ __device__ __forceinline__ void prep_one(const ProbDesc& P, int mat, double* col
       __syncthreads();
     }
     if (threadIdx.x == 0) P.norms[mat] = colmax[0];
+    if (mat > 0) control_rows<T, D>(P, mat - 1, src);
     __syncthreads();
   } else if (P.Vz != nullptr && P.Vint != nullptr) {
     T* dst = reinterpret_cast<T*>(P.Vint);
@@ -171,7 +221,8 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
 template <typename T, int D, typename Ops, int G = 1>
-__device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk) {
+__device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk,
+                                         bool mono) {
   // The matrix is read as D^2/4 chunks of four consecutive row elements;
   // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
   // lanes of one 16-byte load read consecutive chunks.  The loads of G
@@ -179,6 +230,9 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
   // clamped to it and weighted by zero, which leaves every sum unchanged.
   // Chunks are written to LDS four columns at a time.  When hk is not null,
   // H_k itself is also written there (planar, row-major) for the adjoint.
+  // With mono (every control has at most one nonzero per row) each chunk
+  // takes its row's entry of each control from the row tables instead: the
+  // same products, minus those with structural zeros.
   using v4 = typename Prec<T>::v4;
   constexpr int NV = D / 16;
   constexpr int NT = 4 * D;
@@ -190,6 +244,38 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     hr[v] = Prec<T>::gld4(H + e0 + 4 * NT * v);
     hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
   }
+  if (mono) {
+    constexpr int GM = 4;  // controls whose table entries are loaded together
+    const T* mv = reinterpret_cast<const T*>(P.mval);
+    for (int j0 = 0; j0 < P.m; j0 += GM) {
+      int col[GM][NV];
+      T vr[GM][NV], vi[GM][NV], uw[GM];
+#pragma unroll
+      for (int jj = 0; jj < GM; ++jj) {
+        const int j = min(j0 + jj, P.m - 1);
+        uw[jj] = j0 + jj < P.m ? (T)gp(P.u)[(size_t)j * P.N + k] : (T)0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const size_t idx = (size_t)j * D + (e0 + 4 * NT * v) / D;
+          col[jj][v] = gp(P.mcol)[idx];
+          vr[jj][v] = gp(mv)[2 * idx];
+          vi[jj][v] = gp(mv)[2 * idx + 1];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < GM; ++jj)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int c0 = (e0 + 4 * NT * v) % D;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T w = col[jj][v] == c0 + i ? uw[jj] : (T)0;
+            hr[v][i] += w * vr[jj][v];
+            hi[v][i] += w * vi[jj][v];
+          }
+        }
+    }
+  } else
   for (int j0 = 0; j0 < P.m; j0 += G) {
     v4 ar[G][NV], ai[G][NV];
     T uw[G];
@@ -376,18 +462,45 @@ __device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j
 // wavefront has finished its products), so that thread t owns the chunks of
 // four consecutive row elements t, t + 4D, t + 8D, ... and reads each
 // control's matching chunks with 16-byte loads, consecutive across lanes.
+// With mono (every control has at most one nonzero per row), Tr(Z^dag Hc[j])
+// is the sum over rows a of conj(Z[a][col_j(a)]) val_j(a): thread t takes row
+// t % D of control j0 + t / D of each group of four controls.
 template <typename T, int D>
 __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, const Panel<T, D>& Z, const Lane& L,
-                                                  void* lds, double* red) {
+                                                  void* lds, double* red, bool mono) {
   using v4 = typename Prec<T>::v4;
   constexpr int NV = D / 16;
   constexpr int EPT = 4 * NV;
   constexpr int NT = 4 * D;
   constexpr int SD = Mat<T, D>::SD;
+  static_assert(NT == kEpiGroup * D, "one (control, row) pair per thread");
   T* zl = static_cast<T*>(lds);
   __syncthreads();  // every wavefront is done with the left factors
   panel_to_lds(zl, Z, L);
   __syncthreads();
+  if (mono) {
+    const int a = threadIdx.x % D, jj = threadIdx.x / D;
+    const T* mv = reinterpret_cast<const T*>(P.mval);
+    for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
+      double v[2 * kEpiGroup];
+      double tr = 0, ti = 0;
+      if (j0 + jj < P.m) {
+        const size_t idx = (size_t)(j0 + jj) * D + a;
+        const int off = lds_off<T, D>(a, gp(P.mcol)[idx]);
+        const double zr = (double)zl[off], zi = (double)zl[D * SD + off];
+        const double x = (double)gp(mv)[2 * idx], y = (double)gp(mv)[2 * idx + 1];
+        tr = zr * x + zi * y;  // conj(z) h
+        ti = zr * y - zi * x;
+      }
+#pragma unroll
+      for (int q = 0; q < kEpiGroup; ++q) {
+        v[2 * q] = q == jj ? tr : 0.0;
+        v[2 * q + 1] = q == jj ? ti : 0.0;
+      }
+      epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
+    }
+    return;
+  }
   const int e0 = 4 * threadIdx.x;
   double zr[EPT], zi[EPT];
 #pragma unroll
@@ -467,7 +580,7 @@ void k_expm(Work W) {
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
   T* hk = (kKeepH<D> && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
-  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk);
+  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk, controls_monomial<D>(P));
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
@@ -730,6 +843,7 @@ void k_adjoint(Work W) {
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
+  const bool mono = controls_monomial<D>(P);
   Panel<T, D> R1, R2, A1, A2;
 
   // 1. W = bloc[k] xprev[k]^dag (bloc carries mc[c]).  The slice's global
@@ -754,7 +868,7 @@ void k_adjoint(Work W) {
     if constexpr (!kEarlyH<T, D>) ham_load<T, D>(ham, pf_mat<T, D>(P.hk, k - W.rg.kbase));
     ham_put<T, D, Ops>(lds[0], ham, ldexp(P.dt, -s), -1.0);
   } else {
-    assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr);
+    assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr, mono);
   }
   __syncthreads();
   const void* X = lds[0];
@@ -797,7 +911,7 @@ void k_adjoint(Work W) {
   }
 
   // 5. inner products with the controls (FP64), then the gradient
-  gradient_epilogue<T, D>(P, k, A2, L, lds[0], red);
+  gradient_epilogue<T, D>(P, k, A2, L, lds[0], red, mono);
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
   }

@@ -70,7 +70,7 @@ class Options(ctypes.Structure):
         ("reunitarise_tol", ctypes.c_double),
         ("stream", ctypes.c_void_p),
         ("chunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("dense_controls", ctypes.c_int32),
         ("diagnostics", ctypes.c_void_p),
     ]
 
@@ -134,7 +134,7 @@ def _check(rc: int):
         raise QocError(rc, lib().qoc_last_error().decode())
 
 
-def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0) -> Options:
+def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0, dense_controls=False) -> Options:
     o = Options()
     lib().qoc_default_options(ctypes.byref(o))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -142,6 +142,7 @@ def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0
     o.chunk = int(chunk)
     o.stream = stream
     o.hbm_budget = int(hbm_budget)
+    o.dense_controls = 1 if dense_controls else 0
     return o
 
 
@@ -159,32 +160,32 @@ def _ptr(a: np.ndarray):
 
 # ------------------------------------------------------------ host entry points
 
-def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0, hbm_budget=0) -> np.ndarray:
+def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False) -> np.ndarray:
     """X_N = U_{N-1} ... U_0 (host arrays in, host array out)."""
     H0, Hc, u = _c128(H0), _c128(Hc), _f64(u)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     out = np.empty((d, d), dtype=np.complex128)
-    o = options(precision, validate, chunk, None, hbm_budget)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
     _check(lib().qoc_propagate(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(out), ctypes.byref(o)))
     return out
 
 
-def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0) -> float:
+def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False) -> float:
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
-    o = options(precision, validate, chunk, None, hbm_budget)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
     _check(lib().qoc_fidelity(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), ctypes.byref(o)))
     return float(F[0])
 
 
-def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0):
+def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False):
     """(F, grad) with grad[j, k] = dF/du[j, k]."""
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
     grad = np.empty((m, N))
-    o = options(precision, validate, chunk, None, hbm_budget)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
     _check(lib().qoc_gradient(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), _ptr(grad),
                               ctypes.byref(o)))
     return float(F[0]), grad
@@ -250,13 +251,14 @@ class Batch:
 class Runner:
     """Owns a device workspace for repeated calls on batches of one shape."""
 
-    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda", hbm_budget=0):
+    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda", hbm_budget=0, dense_controls=False):
         import torch
 
         self.B, self.d, self.m, self.N = B, d, m, N
         self.precision = precision
         self.chunk = chunk
         self.hbm_budget = int(hbm_budget)
+        self.dense_controls = bool(dense_controls)
         self.ws_bytes = workspace_size(B, d, m, N, precision, chunk, hbm_budget)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.device = device
@@ -265,7 +267,8 @@ class Runner:
         import torch
 
         st = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
-        return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream), self.hbm_budget)
+        return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream), self.hbm_budget,
+                       self.dense_controls)
 
     def _shape_ok(self, b: Batch):
         if (b.B, b.d, b.m, b.N) != (self.B, self.d, self.m, self.N):

@@ -33,6 +33,7 @@ def test_version_and_defaults():
     assert "libqoc" in qoc.version()
     o = qoc.options()
     assert o.precision == qoc.FP64 and o.chunk == 0 and o.reunitarise_tol == 0.0 and not o.diagnostics
+    assert o.dense_controls == 0 and qoc.options(dense_controls=True).dense_controls == 1
 
 
 def _err(fn, *a):

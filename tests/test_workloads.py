@@ -2,7 +2,7 @@
 determinism (every consumer must see the same problem)."""
 import numpy as np
 
-from workloads import make_config, make_random, make_request, poisson_trace
+from workloads import make_config, make_random, make_random_monomial, make_request, poisson_trace
 
 
 def _check(p):
@@ -22,6 +22,22 @@ def test_generators_are_hermitian_unitary_and_deterministic():
         assert np.array_equal(p.H0, q.H0) and np.array_equal(p.Hc, q.Hc)
         assert np.array_equal(p.u, q.u) and np.array_equal(p.V, q.V)
     assert not np.array_equal(make_random(3, 29, 3, 11, 0.02).u, make_random(4, 29, 3, 11, 0.02).u)
+
+
+def test_monomial_controls_have_one_nonzero_per_row_at_most():
+    for d in (1, 2, 5, 16, 33, 64):
+        p = make_random_monomial(2, d, 4, 10, 0.05)
+        q = make_random_monomial(2, d, 4, 10, 0.05)
+        _check(p)
+        assert np.array_equal(p.Hc, q.Hc) and np.array_equal(p.u, q.u)
+        for H in p.Hc:
+            assert np.all(np.count_nonzero(H, axis=1) <= 1)
+            assert np.all(np.count_nonzero(H, axis=0) <= 1)
+    # every kind of row occurs: paired, diagonal and empty
+    H = np.concatenate(list(make_random_monomial(2, 64, 4, 10, 0.05).Hc))
+    nz = np.count_nonzero(H, axis=1)
+    assert (nz == 0).any() and (nz == 1).any()
+    assert any(np.count_nonzero(np.diag(h)) > 0 for h in make_random_monomial(2, 64, 4, 10, 0.05).Hc)
 
 
 def test_poisson_trace_shapes_do_not_depend_on_the_rate():

@@ -18,7 +18,9 @@ from .spin import (
     make_batch,
     make_request,
     make_random,
+    make_random_monomial,
     random_hermitian,
+    random_monomial_hermitian,
     poisson_trace,
     SERVE_DIMS,
     SERVE_WEIGHTS,
@@ -36,7 +38,9 @@ __all__ = [
     "make_batch",
     "make_request",
     "make_random",
+    "make_random_monomial",
     "random_hermitian",
+    "random_monomial_hermitian",
     "poisson_trace",
     "SERVE_DIMS",
     "SERVE_WEIGHTS",

@@ -193,6 +193,43 @@ SERVE_DIMS = (2, 4, 8, 16, 32, 64, 128)
 SERVE_WEIGHTS = (0.10, 0.15, 0.20, 0.20, 0.15, 0.12, 0.08)
 
 
+def random_monomial_hermitian(d: int, rng: np.random.Generator) -> np.ndarray:
+    """A Hermitian matrix with at most one nonzero per row (a phased involution,
+    as a Pauli string is): rows are paired by a random involution; a pair (a, b)
+    gets H[a, b] = z and H[b, a] = conj(z) with z of unit modulus times a
+    uniform factor in [0.5, 1.5], a fixed point a a real H[a, a] in
+    [-1.5, 1.5], and with probability 0.1 a row is left empty."""
+    H = np.zeros((d, d), dtype=np.complex128)
+    order = rng.permutation(d)
+    i = 0
+    while i < d:
+        a = int(order[i])
+        if rng.random() < 0.1:
+            i += 1  # an empty row (and column)
+        elif i + 1 < d and rng.random() < 0.7:
+            b = int(order[i + 1])
+            z = rng.uniform(0.5, 1.5) * np.exp(1j * rng.uniform(0, 2 * np.pi))
+            H[a, b] = z
+            H[b, a] = np.conj(z)
+            i += 2
+        else:
+            H[a, a] = rng.uniform(-1.5, 1.5)
+            i += 1
+    return H
+
+
+def make_random_monomial(seed: int, d: int, m: int, N: int, dt: float, u_scale: float = 0.5) -> Problem:
+    """A problem with a dense random Hermitian drift, m controls of
+    random_monomial_hermitian, u ~ N(0, u_scale) and a Haar target; seeded with
+    SeedSequence([seed, d, m, N, 1]) and drawn in the order H0, Hc, u, V."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, d, m, N, 1]))
+    H0 = random_hermitian(d, rng)
+    Hc = np.stack([random_monomial_hermitian(d, rng) for _ in range(m)])
+    u = rng.normal(0.0, u_scale, size=(m, N))
+    V = haar_unitary(d, rng)
+    return Problem(H0, Hc, u, dt, V, f"monomial{seed}.{d}x{m}x{N}")
+
+
 def make_request(index: int, d: int, N: int, trace_seed: int = 5) -> Problem:
     """One serving request: Heisenberg chain on log2(d) qubits (d = 2: the
     drift is h_0 Z_0 alone), 2 log2(d) controls, u ~ N(0, 0.5), dt = 0.005,
