@@ -76,12 +76,12 @@ typedef struct {
                              never applied in FP64. */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
   int32_t chunk;          /* slices per scan chunk; 0 = ceil(sqrt(N)) */
-  int32_t dense_controls; /* 0 (default): at d <= 64, when every control Hc[j] has at
-                             most one nonzero per row (Pauli strings, for instance),
-                             the slice Hamiltonians are assembled and the gradient's
-                             inner products Tr(Z_k^dag Hc[j]) taken entry by entry,
-                             O(d) per control instead of O(d^2), with the same terms;
-                             nonzero: always the dense kernels */
+  int32_t dense_controls; /* 0 (default): when every control Hc[j] has at most one
+                             nonzero per row (Pauli strings, for instance), the slice
+                             Hamiltonians are assembled and (except FP64 at d > 64)
+                             the gradient's inner products Tr(Z_k^dag Hc[j]) taken
+                             entry by entry, O(d) per control instead of O(d^2),
+                             with the same terms; nonzero: always the dense kernels */
   double* diagnostics;    /* optional, 4 doubles per problem (device memory for _dev calls,
                              host memory for host calls): [0] |X_N^dag X_N - I|_F,
                              [1] largest chunk residual r, [2] number of Newton-Schulz

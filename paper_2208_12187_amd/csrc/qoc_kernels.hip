@@ -78,7 +78,7 @@ __device__ __forceinline__ T* pf_mat(void* base, int i) {
 
 // ---------------------------------------------------------------- prep
 
-// Row table of control j (D <= 64): for each row a, the column and value (in
+// Row table of control j: for each row a, the column and value (in
 // precision T, as the dense copy holds it) of its nonzero, and whether every
 // row has at most one.  Such controls (Pauli strings, for instance) are then
 // assembled and paired with Z_k entry by entry.  The table is written even
@@ -88,7 +88,7 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
   const int d = P.d;
   const int a = threadIdx.x;
   int multi = 0;
-  if constexpr (D <= 64) {
+  {
     if (a < D) {
       int col = a, cnt = 0;
       T vr = 0, vi = 0;
@@ -110,21 +110,16 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
     }
   }
   const int any = __syncthreads_or(multi);
-  if (threadIdx.x == 0) gp(P.mok)[j] = (D <= 64 && !any && !(P.flags & CTRL_DENSE)) ? 1 : 0;
+  if (threadIdx.x == 0) gp(P.mok)[j] = (!any && !(P.flags & CTRL_DENSE)) ? 1 : 0;
 }
 
-// True when every control of the problem has a usable row table (D <= 64,
-// at most one nonzero per row, dense kernels not forced).  Uniform across
-// the workgroup.
-template <int D>
+// True when every control of the problem has a usable row table (at most
+// one nonzero per row, dense kernels not forced).  Uniform across the
+// workgroup.
 __device__ __forceinline__ bool controls_monomial(const ProbDesc& P) {
-  if constexpr (D > 64) {
-    return false;
-  } else {
-    for (int j = 0; j < P.m; ++j)
-      if (!gp(P.mok)[j]) return false;
-    return true;
-  }
+  for (int j = 0; j < P.m; ++j)
+    if (!gp(P.mok)[j]) return false;
+  return true;
 }
 
 // Convert the caller's complex128 matrices to the compute precision: H0 and
@@ -580,7 +575,7 @@ void k_expm(Work W) {
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
   T* hk = (kKeepH<D> && (P.flags & RUN_GRAD)) ? pf_mat<T, D>(P.hk, k - W.rg.kbase) : nullptr;
-  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk, controls_monomial<D>(P));
+  assemble<T, D, Ops>(lds, P, k, ldexp(P.dt, -s), 1.0, hk, controls_monomial(P));
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
@@ -843,7 +838,7 @@ void k_adjoint(Work W) {
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
-  const bool mono = controls_monomial<D>(P);
+  const bool mono = controls_monomial(P);
   Panel<T, D> R1, R2, A1, A2;
 
   // 1. W = bloc[k] xprev[k]^dag (bloc carries mc[c]).  The slice's global
@@ -1112,9 +1107,13 @@ __device__ __forceinline__ void transpose128(T* out, T* lds, const T* M, const L
 // pass (one FP64 matrix does not fit in LDS); FP64 writes each half's rows of
 // the panel to out and reads the panel back at the end, so that no panel is
 // held across the passes.  Starts and ends with a workgroup barrier.
+// With mono (every control has at most one nonzero per row) the chunks of H0
+// go to LDS unscaled, one thread per row then adds the row's entry of each
+// control in turn (the same sums, minus the structural zeros), and a last
+// pass over the chunks applies the scale.
 template <typename T>
 __device__ __forceinline__ void assemble128(Panel<T, 128>& X, T* out, T* lds, const ProbDesc& P, int k, double c,
-                                            double sgn, const Lane& L) {
+                                            double sgn, const Lane& L, bool mono) {
   using v4 = typename Prec<T>::v4;
   constexpr int D = 128, NT = 512;
   constexpr int PASSES = sizeof(T) == 4 ? 1 : 2;
@@ -1134,6 +1133,7 @@ __device__ __forceinline__ void assemble128(Panel<T, 128>& X, T* out, T* lds, co
       hr[v] = Prec<T>::gld4(H + e0 + 4 * NT * v);
       hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
     }
+    if (!mono)
     for (int j = 0; j < P.m; ++j) {
       const T uj = (T)gp(P.u)[(size_t)j * P.N + k];
       const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
@@ -1150,15 +1150,56 @@ __device__ __forceinline__ void assemble128(Panel<T, 128>& X, T* out, T* lds, co
       }
     }
     __syncthreads();  // LDS free
+    if (mono) {
+      // H0 unscaled, then each row's control entries, then the scale
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int e = e0 + 4 * NT * v;
-      const int row = e / D - pass * ROWS, col = e % D;
+      for (int v = 0; v < NV; ++v) {
+        const int e = e0 + 4 * NT * v;
+        const int row = e / D - pass * ROWS, col = e % D;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int off = row * SD + ((col + i) & ~15) + Prec<T>::perm((col + i) & 15);
-        lds[off] = f * hi[v][i];   // -i f (hr + i hi)
-        lim[off] = -f * hr[v][i];
+        for (int i = 0; i < 4; ++i) {
+          const int off = row * SD + ((col + i) & ~15) + Prec<T>::perm((col + i) & 15);
+          lds[off] = hr[v][i];
+          lim[off] = hi[v][i];
+        }
+      }
+      __syncthreads();
+      if ((int)threadIdx.x < ROWS) {
+        const int a = pass * ROWS + threadIdx.x;
+        const T* mv = reinterpret_cast<const T*>(P.mval);
+        for (int j = 0; j < P.m; ++j) {
+          const T uj = (T)gp(P.u)[(size_t)j * P.N + k];
+          const size_t idx = (size_t)j * D + a;
+          const int col = gp(P.mcol)[idx];
+          const int off = (int)threadIdx.x * SD + (col & ~15) + Prec<T>::perm(col & 15);
+          lds[off] += uj * gp(mv)[2 * idx];
+          lim[off] += uj * gp(mv)[2 * idx + 1];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int e = e0 + 4 * NT * v;
+        const int row = e / D - pass * ROWS, col = e % D;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int off = row * SD + ((col + i) & ~15) + Prec<T>::perm((col + i) & 15);
+          const T r = lds[off], im = lim[off];
+          lds[off] = f * im;  // -i f (r + i im)
+          lim[off] = -f * r;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int e = e0 + 4 * NT * v;
+        const int row = e / D - pass * ROWS, col = e % D;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int off = row * SD + ((col + i) & ~15) + Prec<T>::perm((col + i) & 15);
+          lds[off] = f * hi[v][i];   // -i f (hr + i hi)
+          lim[off] = -f * hr[v][i];
+        }
       }
     }
     __syncthreads();
@@ -1193,11 +1234,47 @@ __device__ __forceinline__ void assemble128(Panel<T, 128>& X, T* out, T* lds, co
 // pass (one FP64 matrix does not fit in LDS).  Z is read from the PF matrix
 // Zpf, in which every wavefront has stored its own panel (so the staging
 // needs no barrier before its reads and holds no panel in registers).
+// With mono (every control has at most one nonzero per row) thread t takes
+// row t % 128 of control j0 + t / 128 of each group of four controls and
+// reads its one entry of Z from Zpf directly, after a barrier.  FP32 only:
+// the branch doubles the FP64 adjoint's register spills, which costs more
+// than the dense inner products.
 template <typename T>
 __device__ __forceinline__ void gradient_epilogue128(const ProbDesc& P, int k, const T* Zpf, const Lane& L,
-                                                     T* lds, double* red) {
+                                                     T* lds, double* red, bool mono) {
   using v4 = typename Prec<T>::v4;
   constexpr int D = 128, NT = 512, NV = 4;
+  static_assert(NT == kEpiGroup * D, "one (control, row) pair per thread");
+  if (sizeof(T) == 4 && mono) {
+    __syncthreads();  // every wavefront's panel of Z is in Zpf
+    const int a = threadIdx.x % D, jj = threadIdx.x / D;
+    const T* mv = reinterpret_cast<const T*>(P.mval);
+    // PF position of row a: row block, and register / lane group within it
+    const int rb = a >> 4, rr = a & 15;
+    const int g = sizeof(T) == 4 ? rr >> 2 : rr & 3;
+    const int r = sizeof(T) == 4 ? rr & 3 : rr >> 2;
+    for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
+      double v[2 * kEpiGroup];
+      double tr = 0, ti = 0;
+      if (j0 + jj < P.m) {
+        const size_t idx = (size_t)(j0 + jj) * D + a;
+        const int col = gp(P.mcol)[idx];
+        const int lane = 16 * g + (col & 15);
+        const double zr = (double)gp(Zpf)[pf_index<T, D>(col >> 4, 0, 4 * rb + r, lane)];
+        const double zi = (double)gp(Zpf)[pf_index<T, D>(col >> 4, 1, 4 * rb + r, lane)];
+        const double x = (double)gp(mv)[2 * idx], y = (double)gp(mv)[2 * idx + 1];
+        tr = zr * x + zi * y;  // conj(z) h
+        ti = zr * y - zi * x;
+      }
+#pragma unroll
+      for (int q = 0; q < kEpiGroup; ++q) {
+        v[2 * q] = q == jj ? tr : 0.0;
+        v[2 * q + 1] = q == jj ? ti : 0.0;
+      }
+      epilogue_publish<8>(P, k, j0, grp, v, L, red);
+    }
+    return;
+  }
   constexpr bool RESTAGE = sizeof(T) == 8;
   constexpr int ROWS = RESTAGE ? 64 : 128;  // rows staged at once
   constexpr int SD = D + Prec<T>::PAD;
@@ -1300,7 +1377,7 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     int s, q, qb;
     unpack_sq(gp(P.sq)[k], s, q, qb);
     Panel<T, 128> acc;
-    assemble128<T>(acc, SX, lds, P, k, ldexp(P.dt, -s), 1.0, L);  // SX: the left factor of the products
+    assemble128<T>(acc, SX, lds, P, k, ldexp(P.dt, -s), 1.0, L, controls_monomial(P));  // SX: the left factor
     // For the adjoint: X = A_k / 2^s in PF layout (its X, A_k^dag / 2^s, is
     // the exact negation), one coalesced store of this wavefront's panel.
     if (P.flags & RUN_GRAD) panel_store(pf_mat<T, 128>(P.hk, k - W.rg.kbase), acc, L);
@@ -1483,7 +1560,7 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
       }
     }
     panel_store(S0, acc, L);  // Z (own panel)
-    gradient_epilogue128<T>(P, k, S0, L, lds, red);
+    gradient_epilogue128<T>(P, k, S0, L, lds, red, sizeof(T) == 4 && controls_monomial(P));
     __syncthreads();
   }
 }

@@ -25,7 +25,8 @@ def _check(p, prec, F, grad, ref):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("d,m,N", [(2, 3, 37), (5, 4, 50), (16, 6, 61), (23, 5, 40), (33, 7, 45), (64, 12, 70)])
+@pytest.mark.parametrize("d,m,N", [(2, 3, 37), (5, 4, 50), (16, 6, 61), (23, 5, 40), (33, 7, 45), (64, 12, 70),
+                                   (100, 9, 23), (128, 14, 20)])
 def test_monomial_controls_match_the_oracle(gpu_lib, prec, d, m, N):
     from paper_2208_12187_amd import qoc
 
@@ -39,7 +40,7 @@ def test_monomial_controls_match_the_oracle(gpu_lib, prec, d, m, N):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("cfg,N", [(2, 300), (3, 240)])
+@pytest.mark.parametrize("cfg,N", [(2, 300), (3, 240), (4, 40)])
 def test_spin_chain_row_tables_against_dense_kernels(gpu_lib, prec, cfg, N):
     """The spin-chain controls are Pauli strings: the row-table path and the
     dense kernels give the same F (the assembled H_k are equal) and gradients
@@ -57,10 +58,11 @@ def test_spin_chain_row_tables_against_dense_kernels(gpu_lib, prec, cfg, N):
     gmax = np.max(np.abs(ref["grad"]))
     assert abs(F - Fd) <= 1e-14
     assert np.max(np.abs(g - gd)) <= (1e-12 if prec == "fp64" else 1e-6) * gmax
-    if prec == "fp64":
+    if prec == "fp64" and p.d <= 64:
         # the two paths did run: their gradient sums are ordered differently (in
         # FP32 the products of FP32 values are exact in FP64, and so are their
-        # sums often enough that both orders can give the same bits)
+        # sums often enough that both orders can give the same bits; FP64 at
+        # d = 128 takes only the assembly from the row tables)
         assert not np.array_equal(g, gd)
 
 
