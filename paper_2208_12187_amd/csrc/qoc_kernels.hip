@@ -239,7 +239,42 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     hr[v] = Prec<T>::gld4(H + e0 + 4 * NT * v);
     hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
   }
-  if (mono) {
+  const size_t tab_bytes = (size_t)P.m * D * (sizeof(int) + 2 * sizeof(T)) + (size_t)P.m * sizeof(T);
+  if (mono && tab_bytes <= (size_t)Ops::BYTES) {
+    // The problem's row tables and the slice's amplitudes go through LDS (the
+    // left-factor space, written below only after a barrier): one round trip
+    // of coalesced loads instead of one per group of controls.
+    const int mD = P.m * D;
+    int* lc = static_cast<int*>(lds);
+    T* lv = reinterpret_cast<T*>(lc + mD);
+    T* lu = lv + 2 * mD;
+    const T* mv = reinterpret_cast<const T*>(P.mval);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < mD; i += NT) {
+      lc[i] = gp(P.mcol)[i];
+      lv[2 * i] = gp(mv)[2 * i];
+      lv[2 * i + 1] = gp(mv)[2 * i + 1];
+    }
+    for (int j = threadIdx.x; j < P.m; j += NT) lu[j] = (T)gp(P.u)[(size_t)j * P.N + k];
+    __syncthreads();
+    for (int j = 0; j < P.m; ++j) {
+      const T uj = lu[j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int e = e0 + 4 * NT * v;
+        const int idx = j * D + e / D, c0 = e % D;
+        const int col = lc[idx];
+        const T vr = lv[2 * idx], vi = lv[2 * idx + 1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T w = col == c0 + i ? uj : (T)0;
+          hr[v][i] += w * vr;
+          hi[v][i] += w * vi;
+        }
+      }
+    }
+    __syncthreads();  // the tables are read; the LDS takes the left factor next
+  } else if (mono) {
     constexpr int GM = 4;  // controls whose table entries are loaded together
     const T* mv = reinterpret_cast<const T*>(P.mval);
     for (int j0 = 0; j0 < P.m; j0 += GM) {
