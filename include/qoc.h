@@ -75,7 +75,7 @@ typedef struct {
                              0 = default (1e-6 FP32, 1e-4 BF16X3); < 0 disables;
                              never applied in FP64. */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
-  int32_t chunk;          /* slices per scan chunk; 0 = ceil(sqrt(N)) */
+  int32_t chunk;          /* slices per scan chunk; 0 = qoc_default_chunk(d, N) */
   int32_t dense_controls; /* 0 (default): when every control Hc[j] has at most one
                              nonzero per row (Pauli strings, for instance), the slice
                              Hamiltonians are assembled and (except FP64 at d > 64)
@@ -117,6 +117,14 @@ int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const do
  * share a workspace must be ordered on one stream.
  */
 size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget);
+
+/*
+ * Default slices per scan chunk (opt->chunk = 0): ceil(sqrt(N / 2)) for
+ * d <= 64, where the carry over the chunk totals runs in groups of
+ * ceil(sqrt(chunks)), and ceil(sqrt(N)) for 64 < d <= 128, where it is one
+ * serial chain.  0 for d outside [1, 128] or N < 1.
+ */
+int qoc_default_chunk(int d, int N);
 
 int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                       const void* u, double dt, void* U_total, void* workspace,

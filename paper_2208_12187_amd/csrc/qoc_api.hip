@@ -385,6 +385,11 @@ int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const do
                   qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
 }
 
+int qoc_default_chunk(int d, int N) {
+  if (d < 1 || d > 128 || N < 1) return 0;
+  return qoc::default_chunk(qoc::padded_dim(d), N);
+}
+
 size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
   if (check_dims(B, d, m, N, precision)) return 0;
   return make_layout(B, d, m, N, precision, chunk, hbm_budget).total;

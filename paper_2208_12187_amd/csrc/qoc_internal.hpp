@@ -19,6 +19,7 @@ namespace qoc {
 struct ProbDesc {
   int d, D, m, N;  // true dimension, padded dimension, controls, slices
   int L, P;        // slices per scan chunk, number of chunks
+  int CG, PG;      // chunks per carry group, number of carry groups (d <= 64)
   int flags, pad_;
   double dt;
   const double* H0z;  // (user) d*d complex128, interleaved
@@ -44,6 +45,8 @@ struct ProbDesc {
   void* cf;           // P PF matrices: forward carry into each chunk
   void* cb;           // P PF matrices: backward carry out of each chunk
   void* mc;           // P PF matrices: cb[c] cf[c]^dag
+  void* grp;          // 4 x PG PF matrices (d <= 64): forward and backward group totals, then the
+                      // forward and backward carries into each group
   double* g;          // complex128 Tr(V^dag X_N)
   double* diag;       // [0] ||X_N^dag X_N - I||_F; [1] largest chunk residual (FP64
                       // bits, atomic max); [2] re-unitarisation steps (uint64 count)
@@ -128,14 +131,34 @@ inline int padded_dim(int d) {
 
 inline size_t elem_size(int precision) { return precision == 0 ? 8 : 4; }
 
+// Default slices per scan chunk.  The scans' dependency depth is about
+// 2 L + (carry depth): with the grouped carry (D <= 64) that is
+// 2 L + 2 sqrt(N / L), and L = ceil(sqrt(N / 2)) keeps the batched throughput
+// of L = ceil(sqrt(N)) while shortening a single problem's chain; D = 128
+// keeps a serial carry of depth N / L and L = ceil(sqrt(N)).
+inline int default_chunk(int D, int N) {
+  const double x = D == 128 ? (double)N : 0.5 * N;
+  return std::max(1, (int)ceil(sqrt(x)));
+}
+
+// The carry over the P chunk totals (d <= 64) runs in groups of CG =
+// ceil(sqrt(P)) chunks: a serial chain inside every group, one over the PG
+// group totals, then one combination per chunk, so that its depth is about
+// 2 sqrt(P) + 3 products instead of P.
+inline void carry_groups(int P, int& CG, int& PG) {
+  CG = std::max(1, (int)ceil(sqrt((double)P)));
+  PG = (P + CG - 1) / CG;
+}
+
 // Byte offsets of one problem's workspace regions, and the total size.
 struct Layout {
   int D, L, P;
   int esize;  // bytes of one real element of the compute precision
+  int CG, PG;  // carry groups (carry_groups)
   int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
   int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
-  size_t Hint, Vint, norms, mono, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, small;
+  size_t Hint, Vint, norms, mono, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, grp, small;
   int per_slice;  // per-slice arrays: delta, xprev, bloc, and hk at D >= 32
   size_t per_prob;
   size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
@@ -144,23 +167,25 @@ struct Layout {
 
 // hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
 // batch: the per-slice arrays (three stored propagators, and the slice
-// Hamiltonians at D >= 32) plus the four per-chunk arrays.  When the
+// Hamiltonians at D >= 32) plus the four per-chunk and four per-group arrays.  When the
 // full arrays do not fit, slices are processed in segments of G chunks whose
 // per-slice arrays are recomputed for the adjoint pass (sqrt(N)
-// checkpointing: with L = ceil(sqrt(N)) and G = 1 the storage is O(sqrt(N))).
+// checkpointing: with L of order sqrt(N) and G = 1 the storage is O(sqrt(N))).
 inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, uint64_t hbm_budget) {
   Layout Lo;
   Lo.D = padded_dim(d);
   Lo.esize = (int)elem_size(precision);
-  Lo.L = chunk > 0 ? std::min(chunk, N) : (int)ceil(sqrt((double)N));
+  Lo.L = chunk > 0 ? std::min(chunk, N) : default_chunk(Lo.D, N);
   if (Lo.L < 1) Lo.L = 1;
   Lo.P = (N + Lo.L - 1) / Lo.L;
+  carry_groups(Lo.P, Lo.CG, Lo.PG);
   const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
   Lo.G = Lo.P;
   Lo.per_slice = Lo.D >= 32 ? 4 : 3;
-  const double full = (double)B * ((double)Lo.per_slice * N + 4.0 * Lo.P) * (double)mat;
+  const double per_call = 4.0 * Lo.P + 4.0 * Lo.PG;  // per-chunk and per-group arrays, in matrices
+  const double full = (double)B * ((double)Lo.per_slice * N + per_call) * (double)mat;
   if (hbm_budget > 0 && full > (double)hbm_budget) {
-    const double avail = (double)hbm_budget / B - 4.0 * Lo.P * (double)mat;
+    const double avail = (double)hbm_budget / B - per_call * (double)mat;
     const double per_chunk = (double)Lo.per_slice * Lo.L * (double)mat;
     Lo.G = avail >= per_chunk ? (int)std::min<double>(Lo.P, floor(avail / per_chunk)) : 1;
   }
@@ -179,6 +204,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.cf = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.cb = o; o = align_up(o + (size_t)Lo.P * mat);
   Lo.mc = o; o = align_up(o + (size_t)Lo.P * mat);
+  Lo.grp = o; o = align_up(o + 4 * (size_t)Lo.PG * mat);
   Lo.small = o; o = align_up(o + 128);
   Lo.per_prob = o;
   Lo.desc_bytes = align_up((size_t)B * sizeof(ProbDesc));
@@ -201,6 +227,8 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.N = N;
   P.L = Lo.L;
   P.P = Lo.P;
+  P.CG = Lo.CG;
+  P.PG = Lo.PG;
   P.flags = flags;
   P.dt = dt;
   P.H0z = H0;
@@ -224,6 +252,7 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.cf = pb + Lo.cf;
   P.cb = pb + Lo.cb;
   P.mc = pb + Lo.mc;
+  P.grp = pb + Lo.grp;
   double* small = reinterpret_cast<double*>(pb + Lo.small);
   P.g = small;                    // 2 doubles
   P.F = F ? F : small + 2;        // 1 double

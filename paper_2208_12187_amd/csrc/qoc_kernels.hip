@@ -768,14 +768,75 @@ void k_scan_local(Work W, int bwd) {
   }
 }
 
-// One workgroup per (problem, direction): serial product over chunk totals.
-// Forward: cf[c] = P_{k0(c)-1}, ending with X_N, its fidelity against V (FP64
-// accumulation) and the unitarity residual |X_N^dag X_N - I|_F.  Backward:
-// cb[c] = Q_{k1(c)-1}, starting from V.  The chains are serial and run as one
-// workgroup per problem and direction, so they take the three-product form
-// at D >= 32 regardless of its registers (each step is on the latency path).
+// The carry over the chunk totals, in groups of CG chunks (carry_groups):
+//   k_carry_grp: one workgroup per (group, direction), a serial chain over the
+//     group's chunk totals that stores the carry from the group start into
+//     each chunk (forward cf_loc[c] = tf[c-1] ... tf[g0] into cf, backward
+//     cb_loc[c] = tf[c+1]^dag ... tf[g1-1]^dag into cb) and the group total;
+//   k_carry_top: one workgroup per (problem, direction), a serial chain over
+//     the group totals that stores the carry into each group (forward from I,
+//     ending with X_N, its fidelity and unitarity residual; backward from V);
+//   k_mc: mc[c] = cb[c] cf[c]^dag with cf[c] = cf_loc[c] gcf[g] and
+//     cb[c] = cb_loc[c] gcb[g].
+// The chains are serial and each runs as one workgroup, so they take the
+// three-product form at D >= 32 regardless of its registers.
+
+// n steps of S <- A_i S, storing S before each step to out[i] (i < nstore).
+// A_i is the PF matrix src[i] (stride step) or, with ct, its conjugate
+// transpose.  Double-buffered LDS; the next factor is loaded during a step.
 template <typename T, int D>
-__global__ __launch_bounds__(4 * D) void k_carry(Work W) {
+__device__ __forceinline__ void carry_chain(Panel<T, D>& S, const T* src, int step, int n, bool ct, T* out,
+                                            int ostep, int nstore, T (*lds)[Mat<T, D>::LDS_ELEMS], const Lane& L) {
+  constexpr int EL = Mat<T, D>::ELEMS;
+  Panel<T, D> nxt, acc;
+  if (n > 0) panel_load(nxt, src, L);
+  for (int i = 0; i < nstore || i < n; ++i) {
+    if (i < nstore) panel_store(out + (ptrdiff_t)i * ostep * EL, S, L);
+    if (i >= n) break;
+    T* buf = lds[i & 1];
+    if (ct) panel_to_lds_ct(buf, nxt, L); else panel_to_lds(buf, nxt, L);
+    if (i + 1 < n) panel_load(nxt, src + (ptrdiff_t)(i + 1) * step * EL, L);
+    __syncthreads();
+    if constexpr (D >= 32) cgemm3m(acc, buf, S, L, true); else cgemm(acc, buf, S, L, true);
+    S = acc;
+  }
+}
+
+// Group matrices: [0, PG) forward totals, [PG, 2 PG) backward totals,
+// [2 PG, 3 PG) forward carries, [3 PG, 4 PG) backward carries.
+template <typename T, int D>
+__device__ __forceinline__ T* grp_mat(const ProbDesc& P, int kind, int g) {
+  return pf_mat<T, D>(P.grp, kind * P.PG + g);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(4 * D) void k_carry_grp(Work W) {
+  __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
+  Lane L;
+  const int bwd = blockIdx.y;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
+  int p, g;
+  split_item(item, 0, W.rg.c_n, I.start, I.nprob, p, g);
+  const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
+  const int c0 = g * P.CG;
+  const int n = min(P.CG, P.P - c0);
+  Panel<T, D> S;
+  panel_identity(S, L);
+  if (!bwd) {
+    carry_chain<T, D>(S, pf_mat<T, D>(P.tf, c0), 1, n, false, pf_mat<T, D>(P.cf, c0), 1, n, lds, L);
+    panel_store(grp_mat<T, D>(P, 0, g), S, L);
+  } else {
+    const int c1 = c0 + n - 1;  // the chain runs from the group's last chunk down
+    carry_chain<T, D>(S, pf_mat<T, D>(P.tf, c1), -1, n, true, pf_mat<T, D>(P.cb, c1), -1, n, lds, L);
+    panel_store(grp_mat<T, D>(P, 1, g), S, L);
+  }
+  __syncthreads();
+  }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(4 * D) void k_carry_top(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
   __shared__ double red[2 * NW];
@@ -784,25 +845,11 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
   const Items I(W);
   for (int p = blockIdx.x; p < I.nprob; p += gridDim.x) {
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
-  Panel<T, D> S, nxt, acc;
-  const int nc = P.P;
-  if (bwd) panel_load(S, reinterpret_cast<const T*>(P.Vint), L); else panel_identity(S, L);
-  int c = bwd ? nc - 1 : 0;
-  panel_load(nxt, pf_mat<T, D>(P.tf, c), L);
-  const int steps = bwd ? nc - 1 : nc;
-  for (int i = 0; i < nc; ++i) {
-    panel_store(pf_mat<T, D>(bwd ? P.cb : P.cf, c), S, L);
-    if (i == steps) break;
-    T* buf = lds[i & 1];
-    if (bwd) panel_to_lds_ct(buf, nxt, L); else panel_to_lds(buf, nxt, L);  // backward: tf[c]^dag
-    const int cn = bwd ? c - 1 : c + 1;
-    if (i + 1 < steps) panel_load(nxt, pf_mat<T, D>(P.tf, cn), L);
-    __syncthreads();
-    if constexpr (D >= 32) cgemm3m(acc, buf, S, L, true); else cgemm(acc, buf, S, L, true);
-    S = acc;
-    c = cn;
-  }
+  Panel<T, D> S, acc;
+  const int ng = P.PG;
   if (!bwd) {
+    panel_identity(S, L);
+    carry_chain<T, D>(S, grp_mat<T, D>(P, 0, 0), 1, ng, false, grp_mat<T, D>(P, 2, 0), 1, ng, lds, L);
     fidelity_epilogue<T, D>(P, S, L, red);
     // Unitarity residual of X_N: S^dag S from the conjugate transpose in LDS.
     __syncthreads();
@@ -810,13 +857,18 @@ __global__ __launch_bounds__(4 * D) void k_carry(Work W) {
     __syncthreads();
     cgemm(acc, lds[0], S, L, true);
     residual_epilogue<T, D>(P, acc, L, red);
+  } else {
+    panel_load(S, reinterpret_cast<const T*>(P.Vint), L);
+    carry_chain<T, D>(S, grp_mat<T, D>(P, 1, ng - 1), -1, ng - 1, false, grp_mat<T, D>(P, 3, ng - 1), -1, ng,
+                      lds, L);
   }
   __syncthreads();
   }
 }
 
 // mc[c] = cb[c] cf[c]^dag for every chunk, the start of its backward scan, so
-// that W_k = (local backward product) mc[c] xprev[k]^dag.
+// that W_k = (local backward product) mc[c] xprev[k]^dag; cf[c] and cb[c] are
+// formed here from the in-group carries and the group carries.
 template <typename T, int D>
 __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   __shared__ T lds[2][Mat<T, D>::LDS_ELEMS];
@@ -826,14 +878,30 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
   int p, c;
   split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
-  Panel<T, D> a, b;
-  panel_load(a, pf_mat<T, D>(P.cb, c), L);
+  const int g = c / P.CG;
+  Panel<T, D> a, b, x, y;
+  // cf[c] = cf_loc[c] gcf[g] and cb[c] = cb_loc[c] gcb[g]
+  panel_load(a, pf_mat<T, D>(P.cf, c), L);
+  panel_load(b, pf_mat<T, D>(P.cb, c), L);
+  panel_load(x, grp_mat<T, D>(P, 2, g), L);
+  panel_load(y, grp_mat<T, D>(P, 3, g), L);
   panel_to_lds(lds[0], a, L);
-  panel_load(b, pf_mat<T, D>(P.cf, c), L);
   panel_to_lds(lds[1], b, L);
   __syncthreads();
-  panel_from_lds_ct(b, lds[1], L);
-  cgemm(a, lds[0], b, L, true);
+  if constexpr (D >= 32) {
+    cgemm3m(a, lds[0], x, L, true);
+    cgemm3m(b, lds[1], y, L, true);
+  } else {
+    cgemm(a, lds[0], x, L, true);
+    cgemm(b, lds[1], y, L, true);
+  }
+  // mc[c] = cb[c] cf[c]^dag
+  __syncthreads();
+  panel_to_lds(lds[0], b, L);
+  panel_to_lds(lds[1], a, L);
+  __syncthreads();
+  panel_from_lds_ct(x, lds[1], L);
+  cgemm(a, lds[0], x, L, true);
   panel_store(pf_mat<T, D>(P.mc, c), a, L);
   __syncthreads();
   }
@@ -1652,8 +1720,12 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
       break;
     }
     case ST_CARRY: {
+      int CG, PG;
+      carry_groups(L.uniformP, CG, PG);
+      Work wg = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob * PG, nullptr, Range{0, 0, 0, PG, 0}, nullptr};
+      hipLaunchKernelGGL((k_carry_grp<T, D>), dim3(grid_of(L, wg.total, 0), dirs), dim3(NT), 0, st, wg);
       Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob, nullptr, all, nullptr};
-      hipLaunchKernelGGL((k_carry<T, D>), dim3(grid_of(L, L.nprob, 0), dirs), dim3(NT), 0, st, w);
+      hipLaunchKernelGGL((k_carry_top<T, D>), dim3(grid_of(L, L.nprob, 0), dirs), dim3(NT), 0, st, w);
       break;
     }
     case ST_MC: {

@@ -36,6 +36,7 @@ EXPORTS = (
     "qoc_fidelity",
     "qoc_gradient",
     "qoc_workspace_size",
+    "qoc_default_chunk",
     "qoc_propagate_dev",
     "qoc_fidelity_dev",
     "qoc_gradient_dev",
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
     L.qoc_gradient.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, opt]
     L.qoc_workspace_size.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.c_uint64]
     L.qoc_workspace_size.restype = sz
+    L.qoc_default_chunk.argtypes = [i32, i32]
+    L.qoc_default_chunk.restype = i32
     L.qoc_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, sz, opt]
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
@@ -200,6 +203,14 @@ def slice_plan(H0, Hc, u, dt, precision="fp64", with_gradient=True) -> np.ndarra
     _check(lib().qoc_slice_plan(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), p, 1 if with_gradient else 0,
                                 _ptr(out)))
     return out
+
+
+def default_chunk(d, N) -> int:
+    """Slices per scan chunk when the chunk option is 0."""
+    n = lib().qoc_default_chunk(d, N)
+    if n == 0:
+        _check(-1)
+    return int(n)
 
 
 def workspace_size(B, d, m, N, precision="fp64", chunk=0, hbm_budget=0) -> int:

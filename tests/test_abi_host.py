@@ -65,6 +65,15 @@ def test_argument_errors_before_any_launch():
     assert L.qoc_workspace_size(1, 16, 1, 1, 5, 0, 0) == 0
 
 
+def test_default_chunk():
+    # d <= 64 (grouped carry): ceil(sqrt(N / 2)); d = 128 (serial carry): ceil(sqrt(N))
+    assert qoc.default_chunk(64, 2000) == 32 and qoc.default_chunk(16, 1000) == 23
+    assert qoc.default_chunk(2, 1) == 1 and qoc.default_chunk(5, 3) == 2
+    assert qoc.default_chunk(128, 1000) == 32 and qoc.default_chunk(100, 2000) == 45
+    L = qoc.lib()
+    assert L.qoc_default_chunk(0, 10) == 0 and L.qoc_default_chunk(129, 10) == 0 and L.qoc_default_chunk(8, 0) == 0
+
+
 def test_workspace_size_scales_with_batch_and_precision():
     a = qoc.workspace_size(1, 64, 12, 2000, "fp64")
     b = qoc.workspace_size(4, 64, 12, 2000, "fp64")

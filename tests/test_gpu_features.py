@@ -22,10 +22,12 @@ def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec, seg):
     full = qoc.Runner(2, p.d, p.m, N, prec)
     D = 128 if p.d > 64 else 64 if p.d > 32 else 32 if p.d > 16 else 16
     mat = 2 * D * D * (8 if prec == "fp64" else 4)
-    L = int(np.ceil(np.sqrt(N)))
+    L = qoc.default_chunk(p.d, N)
     P = -(-N // L)
+    CG = int(np.ceil(np.sqrt(P)))
+    PG = -(-P // CG)  # carry groups
     per_slice = 4 if D >= 32 else 3  # stored propagators, and the slice Hamiltonians at D >= 32
-    budget = 2 * (4 * P + seg * per_slice * L + 1) * mat  # segments of `seg` chunks
+    budget = 2 * (4 * P + 4 * PG + seg * per_slice * L + 1) * mat  # segments of `seg` chunks
     small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=budget)
     assert small.ws_bytes < full.ws_bytes
     print(f"[features] checkpoint cfg{cfg} N={N} {prec} seg={seg}: {full.ws_bytes} -> {small.ws_bytes} bytes",
@@ -138,6 +140,8 @@ def test_reunitarisation_check_and_step(gpu_lib, prec):
     """Chunk residuals are measured in FP64 and reported; forcing a
     Newton-Schulz step on every chunk keeps the result within tolerance and
     does not worsen the unitarity of X_N."""
+    from paper_2208_12187_amd import qoc
+
     p = make_config(3, N=400)
     ref = oracle.grape_ref(p)
     F0, g0, rX0, rmax0, n0 = _grad_diag(p, prec, -1.0)   # check off
@@ -145,7 +149,7 @@ def test_reunitarisation_check_and_step(gpu_lib, prec):
     F2, g2, rX2, rmax2, n2 = _grad_diag(p, prec, 1e-14)  # every chunk
     print(f"[features] {prec}: residual X_N off={rX0:.2e} default={rX1:.2e} forced={rX2:.2e}, "
           f"max chunk residual {rmax1:.2e}, steps default={n1} forced={n2}", flush=True)
-    L = int(np.ceil(np.sqrt(p.N)))
+    L = qoc.default_chunk(p.d, p.N)
     P = -(-p.N // L)
     assert n0 == 0 and rmax0 == 0.0
     assert 0 < rmax1 < 1e-3
