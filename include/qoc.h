@@ -120,9 +120,10 @@ size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, 
 
 /*
  * Default slices per scan chunk (opt->chunk = 0): ceil(sqrt(N / 2)) for
- * d <= 64, where the carry over the chunk totals runs in groups of
- * ceil(sqrt(chunks)), and ceil(sqrt(N)) for 64 < d <= 128, where it is one
- * serial chain.  0 for d outside [1, 128] or N < 1.
+ * d <= 64, ceil(sqrt(N)) for 64 < d <= 128.  The carry over the chunk totals
+ * runs in groups of ceil(sqrt(chunks)), so a problem's chain of dependent
+ * products is about 2 chunk + 2 sqrt(chunks) long.  0 for d outside [1, 128]
+ * or N < 1.
  */
 int qoc_default_chunk(int d, int N);
 

@@ -219,7 +219,7 @@ void build_tables(qoc_engine* E, Bucket& b) {
         case ST_PREP: items = r.m + 2; break;
         case ST_PLAN: case ST_EXPM: case ST_ADJ: items = r.N; break;
         case ST_SCAN: case ST_MC: case ST_BSCAN: items = r.lo.P; break;
-        case ST_CARRY: items = r.D == 128 ? 1 : r.lo.PG; break;  // d <= 64: carry groups
+        case ST_CARRY: items = r.lo.PG; break;  // carry groups
       }
       acc += items;
     }

@@ -19,7 +19,7 @@ namespace qoc {
 struct ProbDesc {
   int d, D, m, N;  // true dimension, padded dimension, controls, slices
   int L, P;        // slices per scan chunk, number of chunks
-  int CG, PG;      // chunks per carry group, number of carry groups (d <= 64)
+  int CG, PG;      // chunks per carry group, number of carry groups
   int flags, pad_;
   double dt;
   const double* H0z;  // (user) d*d complex128, interleaved
@@ -45,7 +45,7 @@ struct ProbDesc {
   void* cf;           // P PF matrices: forward carry into each chunk
   void* cb;           // P PF matrices: backward carry out of each chunk
   void* mc;           // P PF matrices: cb[c] cf[c]^dag
-  void* grp;          // 4 x PG PF matrices (d <= 64): forward and backward group totals, then the
+  void* grp;          // 4 x PG PF matrices: forward and backward group totals, then the
                       // forward and backward carries into each group
   double* g;          // complex128 Tr(V^dag X_N)
   double* diag;       // [0] ||X_N^dag X_N - I||_F; [1] largest chunk residual (FP64
@@ -132,16 +132,16 @@ inline int padded_dim(int d) {
 inline size_t elem_size(int precision) { return precision == 0 ? 8 : 4; }
 
 // Default slices per scan chunk.  The scans' dependency depth is about
-// 2 L + (carry depth): with the grouped carry (D <= 64) that is
-// 2 L + 2 sqrt(N / L), and L = ceil(sqrt(N / 2)) keeps the batched throughput
-// of L = ceil(sqrt(N)) while shortening a single problem's chain; D = 128
-// keeps a serial carry of depth N / L and L = ceil(sqrt(N)).
+// 2 L + (carry depth), with the grouped carry 2 L + 2 sqrt(N / L).  For
+// D <= 64, L = ceil(sqrt(N / 2)) keeps the batched throughput of
+// L = ceil(sqrt(N)) while shortening a single problem's chain.  D = 128 keeps
+// ceil(sqrt(N)): its scans run on at most 256 workgroups (one scratch slot
+// each), and the extra chunks of a shorter L cost batches a second round.
 inline int default_chunk(int D, int N) {
-  const double x = D == 128 ? (double)N : 0.5 * N;
-  return std::max(1, (int)ceil(sqrt(x)));
+  return std::max(1, (int)ceil(sqrt(D == 128 ? (double)N : 0.5 * N)));
 }
 
-// The carry over the P chunk totals (d <= 64) runs in groups of CG =
+// The carry over the P chunk totals runs in groups of CG =
 // ceil(sqrt(P)) chunks: a serial chain inside every group, one over the PG
 // group totals, then one combination per chunk, so that its depth is about
 // 2 sqrt(P) + 3 products instead of P.

@@ -1539,8 +1539,47 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
   }
 }
 
+// The grouped carry at D = 128 (the steps of k_carry_grp, k_carry_top and
+// k_mc); every product reads both factors from stored PF matrices.
 template <typename T>
-__global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratch) {
+__device__ __forceinline__ T* grp_mat128(const ProbDesc& P, int kind, int g) {
+  return pf_mat<T, 128>(P.grp, kind * P.PG + g);
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_carry_grp128(Work W, int dirs, void* scratch) {
+  __shared__ T lds[K128<T>::LDS_ELEMS];
+  Lane L;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total * dirs; item += gridDim.x) {
+    const int bwd = item % dirs;
+    int p, g;
+    split_item(item / dirs, 0, W.rg.c_n, I.start, I.nprob, p, g);
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
+    const int c0 = g * P.CG;
+    const int c1 = min(P.P, c0 + P.CG) - 1;
+    Panel<T, 128> acc;
+    panel_identity(acc, L);
+    if (!bwd) {
+      panel_store(pf_mat<T, 128>(P.cf, c0), acc, L);
+      for (int c = c0; c <= c1; ++c) {
+        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cf, c), L, true);
+        panel_store(c < c1 ? pf_mat<T, 128>(P.cf, c + 1) : grp_mat128<T>(P, 0, g), acc, L);
+      }
+    } else {
+      panel_store(pf_mat<T, 128>(P.cb, c1), acc, L);
+      for (int c = c1; c >= c0; --c) {
+        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cb, c), L, true);  // tf[c]^dag cb_loc[c]
+        panel_store(c > c0 ? pf_mat<T, 128>(P.cb, c - 1) : grp_mat128<T>(P, 1, g), acc, L);
+      }
+    }
+    __syncthreads();
+  }
+  (void)scratch;
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_carry_top128(Work W, int dirs, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   __shared__ double red[2 * 8];
   Lane L;
@@ -1548,14 +1587,14 @@ __global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratc
   for (int item = blockIdx.x; item < I.nprob * dirs; item += gridDim.x) {
     const int bwd = item % dirs;
     const ProbDesc P = W.descs[I.desc(item / dirs)];  // a copy: stores cannot alias it
-    const int nc = P.P;
+    const int ng = P.PG;
     Panel<T, 128> acc;
     if (!bwd) {
       panel_identity(acc, L);
-      panel_store(pf_mat<T, 128>(P.cf, 0), acc, L);
-      for (int c = 0; c < nc; ++c) {
-        gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cf, c), L, true);
-        if (c + 1 < nc) panel_store(pf_mat<T, 128>(P.cf, c + 1), acc, L);
+      panel_store(grp_mat128<T>(P, 2, 0), acc, L);
+      for (int g = 0; g < ng; ++g) {
+        gemm128<T, false>(acc, lds, grp_mat128<T>(P, 0, g), grp_mat128<T>(P, 2, g), L, true);
+        if (g + 1 < ng) panel_store(grp_mat128<T>(P, 2, g + 1), acc, L);
       }
       fidelity_epilogue<T, 128>(P, acc, L, red);
       T* SXN = slot_mat<T>(scratch, 0);
@@ -1564,29 +1603,37 @@ __global__ __launch_bounds__(512) void k_carry128(Work W, int dirs, void* scratc
       residual_epilogue<T, 128>(P, acc, L, red);
     } else {
       panel_load(acc, reinterpret_cast<const T*>(P.Vint), L);
-      panel_store(pf_mat<T, 128>(P.cb, nc - 1), acc, L);
-      for (int c = nc - 1; c >= 1; --c) {
-        gemm128<T, true>(acc, lds, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cb, c), L, true);  // tf[c]^dag cb[c]
-        panel_store(pf_mat<T, 128>(P.cb, c - 1), acc, L);
+      panel_store(grp_mat128<T>(P, 3, ng - 1), acc, L);
+      for (int g = ng - 1; g >= 1; --g) {
+        gemm128<T, false>(acc, lds, grp_mat128<T>(P, 1, g), grp_mat128<T>(P, 3, g), L, true);
+        panel_store(grp_mat128<T>(P, 3, g - 1), acc, L);
       }
     }
     __syncthreads();
   }
 }
 
+// mc[c] = cb[c] cf[c]^dag with cf[c] = cf_loc[c] gcf[g], cb[c] = cb_loc[c] gcb[g].
 template <typename T>
 __global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   Lane L;
   T* S0 = slot_mat<T>(scratch, 0);
+  T* S1 = slot_mat<T>(scratch, 1);
+  T* S2 = slot_mat<T>(scratch, 2);
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
     int p, c;
     split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
-    transpose128<T>(S0, lds, pf_mat<T, 128>(P.cf, c), L);
+    const int g = c / P.CG;
     Panel<T, 128> acc;
-    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), S0, L, true);
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cf, c), grp_mat128<T>(P, 2, g), L, true);
+    panel_store(S1, acc, L);  // cf[c]
+    gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.cb, c), grp_mat128<T>(P, 3, g), L, true);
+    panel_store(S2, acc, L);  // cb[c]
+    transpose128<T>(S0, lds, S1, L);
+    gemm128<T, false>(acc, lds, S2, S0, L, true);
     panel_store(pf_mat<T, 128>(P.mc, c), acc, L);
     __syncthreads();
   }
@@ -1774,8 +1821,13 @@ static void stage_128(int stage, const Launch& L, const Range& rg, double ur) {
       break;
     }
     case ST_CARRY: {
+      int CG, PG;
+      carry_groups(L.uniformP, CG, PG);
+      Work wg = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob * PG, nullptr, Range{0, 0, 0, PG, 0}, nullptr};
+      hipLaunchKernelGGL(k_carry_grp128<T>, dim3(grid_of(L, wg.total * dirs, cap)), dim3(512), 0, st, wg, dirs,
+                         L.scratch);
       Work w = L.dyn ? dyn : Work{L.descs, L.nprob, L.nprob, nullptr, all, nullptr};
-      hipLaunchKernelGGL(k_carry128<T>, dim3(grid_of(L, L.nprob * dirs, cap)), dim3(512), 0, st, w, dirs,
+      hipLaunchKernelGGL(k_carry_top128<T>, dim3(grid_of(L, L.nprob * dirs, cap)), dim3(512), 0, st, w, dirs,
                          L.scratch);
       break;
     }

@@ -66,7 +66,7 @@ def test_argument_errors_before_any_launch():
 
 
 def test_default_chunk():
-    # d <= 64 (grouped carry): ceil(sqrt(N / 2)); d = 128 (serial carry): ceil(sqrt(N))
+    # ceil(sqrt(N / 2)) for d <= 64, ceil(sqrt(N)) for d = 128
     assert qoc.default_chunk(64, 2000) == 32 and qoc.default_chunk(16, 1000) == 23
     assert qoc.default_chunk(2, 1) == 1 and qoc.default_chunk(5, 3) == 2
     assert qoc.default_chunk(128, 1000) == 32 and qoc.default_chunk(100, 2000) == 45
