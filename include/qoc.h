@@ -69,7 +69,7 @@ typedef struct {
                              When those arrays exceed it, slices are
                              processed in checkpoint segments and recomputed
                              for the gradient pass (same results, more work). */
-  double reunitarise_tol; /* reduced precision, d <= 64: every chunk product S of the
+  double reunitarise_tol; /* reduced precision: every chunk product S of the
                              scans is checked in FP64, r = |S^dag S - I|_F, and gets one
                              Newton-Schulz step S (3I - S^dag S)/2 when r exceeds it.
                              0 = default (1e-6 FP32, 1e-4 BF16X3); < 0 disables;

@@ -136,7 +136,7 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
   return e;
 }
 
-// Re-unitarisation threshold of a call: off in FP64 and above d = 64.
+// Re-unitarisation threshold of a call: off in FP64.
 double reun_tol(const qoc_options& o) {
   if (o.precision == QOC_FP64 || o.reunitarise_tol < 0) return -1.0;
   if (o.reunitarise_tol > 0) return o.reunitarise_tol;

@@ -1505,9 +1505,105 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
   }
 }
 
+// The re-unitarisation check of a forward chunk total at D = 128 (FP32): as
+// reunitarise(), with G = Y^dag Y formed in FP64 on the vector ALU from Y
+// staged in LDS (one FP64 matrix does not fit there): thread t owns the 4 x 8
+// tile of G at rows 4 (t / 16), columns 8 (t % 16).  When r > tol, the factor
+// (3I - G) / 2 is written in FP32 to Tpf (a PF matrix free during the forward
+// scans) and Y <- Y (3I - G) / 2 replaces the chunk total at Ypf.
+__device__ __noinline__ void reunitarise128(const ProbDesc& P, float* Ypf, float* Tpf, float* lds, double* red,
+                                               const Lane& L) {
+  using K = K128<float>;
+  constexpr int D = 128, SD = K::SD;
+  static_assert(2 * D * SD <= K::LDS_ELEMS, "LDS too small");
+  float* yr = lds;
+  float* yi = lds + D * SD;
+  __syncthreads();  // every wavefront's panel of Y is stored; the LDS is free
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb) {
+    typename Prec<float>::v4 re, im;
+    pf_rb_load<float>(re, im, Ypf, L.w, rb, L.lane);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int off = (16 * rb + Prec<float>::rowmap(r, L.g)) * SD + 16 * L.w + L.c16;
+      yr[off] = re[r];
+      yi[off] = im[r];
+    }
+  }
+  __syncthreads();
+  const int i0 = 4 * (threadIdx.x / 16), j0 = 8 * (threadIdx.x % 16);
+  double gr[4][8], gi[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) gr[a][b] = gi[a][b] = 0.0;
+  for (int k = 0; k < D; ++k) {
+    double ar[4], ai[4], br[8], bi[8];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      ar[a] = (double)yr[k * SD + i0 + a];
+      ai[a] = (double)yi[k * SD + i0 + a];
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      br[b] = (double)yr[k * SD + j0 + b];
+      bi[b] = (double)yi[k * SD + j0 + b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {  // conj(Y[k][i]) Y[k][j]
+        gr[a][b] += ar[a] * br[b] + ai[a] * bi[b];
+        gi[a][b] += ar[a] * bi[b] - ai[a] * br[b];
+      }
+  }
+  const int d = P.d;
+  double e2 = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      if (i0 + a < d && j0 + b < d) {
+        const double xr = gr[a][b] - (i0 + a == j0 + b ? 1.0 : 0.0), xi = gi[a][b];
+        e2 += xr * xr + xi * xi;
+      }
+  e2 = wave_sum(e2);
+  if (L.lane == 0) red[L.w] = e2;
+  __syncthreads();
+  double tot = 0;
+  for (int w = 0; w < 8; ++w) tot += red[w];
+  const double res = sqrt(tot);
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(&P.diag[1]), (unsigned long long)__double_as_longlong(res));
+  if (res > P.reun_tol) {
+    // T = (3I - G) / 2 in PF layout: row i is register 4 (i / 16) + r of lane
+    // group g (rowmap), column j is lane 16 g + j % 16 of panel j / 16
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + a, rr = i & 15;
+      const int g = rr >> 2, r = rr & 3;  // FP32 rowmap(r, g) = 4 g + r
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int j = j0 + b;
+        const int lane = 16 * g + (j & 15);
+        gp(Tpf)[pf_index<float, D>(j >> 4, 0, 4 * (i >> 4) + r, lane)] =
+            (float)(0.5 * ((i == j ? 3.0 : 0.0) - gr[a][b]));
+        gp(Tpf)[pf_index<float, D>(j >> 4, 1, 4 * (i >> 4) + r, lane)] = (float)(-0.5 * gi[a][b]);
+      }
+    }
+    __syncthreads();  // the factor is complete
+    Panel<float, D> acc;
+    gemm128<float, false>(acc, lds, Ypf, Tpf, L, true);  // Y (3I - G) / 2
+    panel_store(Ypf, acc, L);
+    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&P.diag[2]), 1ull);
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
+  __shared__ double red[8];
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -1525,6 +1621,10 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
         gemm128<T, false>(acc, lds, pf_mat<T, 128>(P.delta, k - W.rg.kbase), cur, L, true);
         panel_axpy_pf(acc, (T)1, cur, L);
         panel_store(k + 1 < k1 ? pf_mat<T, 128>(P.xprev, k + 1 - W.rg.kbase) : pf_mat<T, 128>(P.tf, c), acc, L);
+      }
+      if constexpr (sizeof(T) == 4) {
+        if (P.reun_tol >= 0)
+          reunitarise128(P, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cf, c), reinterpret_cast<float*>(lds), red, L);
       }
     } else {
       panel_store(pf_mat<T, 128>(P.bloc, k1 - 1 - W.rg.kbase), acc, L);

@@ -135,14 +135,14 @@ def _grad_diag(p, prec, tol):
     return F[0], grad, diag[0], diag[1], int(diag[2:3].view(np.uint64)[0])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_reunitarisation_check_and_step(gpu_lib, prec):
+@pytest.mark.parametrize("cfg,N,prec", [(3, 400, "fp32"), (3, 400, "bf16x3"), (4, 120, "fp32")])
+def test_reunitarisation_check_and_step(gpu_lib, cfg, N, prec):
     """Chunk residuals are measured in FP64 and reported; forcing a
     Newton-Schulz step on every chunk keeps the result within tolerance and
-    does not worsen the unitarity of X_N."""
+    does not worsen the unitarity of X_N (d = 64 and d = 128)."""
     from paper_2208_12187_amd import qoc
 
-    p = make_config(3, N=400)
+    p = make_config(cfg, N=N)
     ref = oracle.grape_ref(p)
     F0, g0, rX0, rmax0, n0 = _grad_diag(p, prec, -1.0)   # check off
     F1, g1, rX1, rmax1, n1 = _grad_diag(p, prec, 0.0)    # default threshold
