@@ -78,6 +78,25 @@ def test_chunking_does_not_change_the_result(gpu_lib, chunk):
     _check(F, grad, ref, "fp64")
 
 
+@pytest.mark.parametrize("cfg,d", [(2, 16), (3, 64), (4, 128)])
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 10, 17])
+def test_grouped_carry_against_the_oracle(gpu_lib, cfg, d, P):
+    """The carry over P chunk totals runs in groups of ceil(sqrt(P)) chunks:
+    P = 1 (one group of one), perfect squares (full groups), and P whose last
+    group is partial or a single chunk, in FP64 and FP32."""
+    from paper_2208_12187_amd import qoc
+
+    N = 3 * P if d == 128 else 4 * P - 1  # chunks of 3 or 4 slices, the last one shorter at d < 128
+    chunk = 3 if d == 128 else 4
+    p = make_config(cfg, N=N)
+    assert -(-N // chunk) == P
+    print(f"[parity] grouped carry d={d} P={P} N={N}", flush=True)
+    ref = oracle.grape_ref(p)
+    for prec in ("fp64", "fp32"):
+        F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec, chunk=chunk)
+        _check(F, grad, ref, prec)
+
+
 @pytest.mark.parametrize("d", [3, 5, 20, 48])
 def test_non_power_of_two_dimensions_are_padded_exactly(gpu_lib, d):
     from paper_2208_12187_amd import qoc
