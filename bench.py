@@ -57,13 +57,14 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
 
 
 def time_runner(qoc, torch, runner, batch, steps, warmup):
+    """Times `steps` steps (events between steps only), then runs as many
+    again with libqoc's per-stage events for the stage breakdown, so that
+    those events do not add to the timed steps."""
     F = torch.empty(batch.B, dtype=torch.float64, device="cuda")
     grad = torch.empty((batch.B, batch.m, batch.N), dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         runner.gradient(batch, F, grad)
     torch.cuda.synchronize()
-    qoc.stage_times()
-    qoc.stage_timing(True)
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -74,6 +75,11 @@ def time_runner(qoc, torch, runner, batch, steps, warmup):
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    qoc.stage_times()
+    qoc.stage_timing(True)
+    for _ in range(steps):
+        runner.gradient(batch, F, grad)
+    torch.cuda.synchronize()
     qoc.stage_timing(False)
     stages = qoc.stage_times()
     ms = ev[0].elapsed_time(ev[-1]) / steps
