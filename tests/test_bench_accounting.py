@@ -47,3 +47,16 @@ def test_three_product_form_is_counted_where_used():
     assert f["scan"] == 2 * 8.0 * 128 ** 3 * 2
     f = bench.slice_flops(plan, 128, 14, "fp64")
     assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * 128 ** 3 * 5
+
+
+def test_more_than_one_gpu_is_refused():
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout + r.stderr
+    assert '"metric"' not in r.stdout
