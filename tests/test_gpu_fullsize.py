@@ -12,6 +12,10 @@ Frechet derivative of the exponential of a skew-Hermitian matrix does not
 increase the 2-norm).  A member run alone gives the same bits as in the
 batch.
 
+Configuration 4 (7-qubit Heisenberg chain, d = 128, m = 14, N = 1000) is
+checked the same way at its benchmark batch of 8, with one member against
+the oracle.
+
 The split-BF16 path keeps about 16 bits per product.  At this size its F
 meets the gate, but its gradient does not for every member: on member 31,
 whose gradient is small (max|grad| = 2.5e-8), the error is 3.6e-4 of
@@ -47,12 +51,12 @@ def _run_batch(problems, prec):
     import torch
     from paper_2208_12187_amd import qoc
 
-    p = problems[0]
-    print(f"[fullsize] config 3, batch {B}, {prec}", flush=True)
+    p, nb = problems[0], len(problems)
+    print(f"[fullsize] d = {p.d}, N = {p.N}, batch {nb}, {prec}", flush=True)
     batch = qoc.Batch.from_problems(problems)
-    runner = qoc.Runner(B, p.d, p.m, p.N, prec)
-    F = torch.empty(B, dtype=torch.float64, device="cuda")
-    grad = torch.empty((B, p.m, p.N), dtype=torch.float64, device="cuda")
+    runner = qoc.Runner(nb, p.d, p.m, p.N, prec)
+    F = torch.empty(nb, dtype=torch.float64, device="cuda")
+    grad = torch.empty((nb, p.m, p.N), dtype=torch.float64, device="cuda")
     runner.gradient(batch, F, grad)
     F1, g1 = F.clone(), grad.clone()
     runner.gradient(batch, F, grad)  # the same workspace again
@@ -61,9 +65,18 @@ def _run_batch(problems, prec):
     return F.cpu().numpy(), grad.cpu().numpy()
 
 
+def _properties(problems, Fh, gh):
+    assert np.all(np.isfinite(gh))
+    for i, q in enumerate(problems):
+        assert 0.0 <= Fh[i] <= 1.0
+        norms = np.linalg.norm(q.Hc, ord=2, axis=(1, 2))
+        bound = 2 * np.sqrt(Fh[i]) * q.dt * norms[:, None] * (1 + 1e-6) + 1e-12
+        assert np.all(np.abs(gh[i]) <= bound), i
+
+
 def _grad_gate(gh, refs, prec):
     gtol = TOL[prec][1]
-    for i in SAMPLED:
+    for i in refs:
         gmax = np.max(np.abs(refs[i]["grad"]))
         err = np.max(np.abs(gh[i] - refs[i]["grad"]))
         print(f"[fullsize] {prec} problem {i}: grad err {err / gmax:.2e} of max|grad| {gmax:.2e}", flush=True)
@@ -84,12 +97,7 @@ def test_config3_batch_of_32(gpu_lib, problems, refs, prec):
     if prec != "bf16x3":
         _grad_gate(gh, refs, prec)
 
-    assert np.all(np.isfinite(gh))
-    for i, q in enumerate(problems):
-        assert 0.0 <= Fh[i] <= 1.0
-        norms = np.linalg.norm(q.Hc, ord=2, axis=(1, 2))
-        bound = 2 * np.sqrt(Fh[i]) * q.dt * norms[:, None] * (1 + 1e-6) + 1e-12
-        assert np.all(np.abs(gh[i]) <= bound), i
+    _properties(problems, Fh, gh)
 
     i = SAMPLED[1]
     alone = qoc.Runner(1, p.d, p.m, p.N, prec)
@@ -103,3 +111,27 @@ def test_config3_batch_of_32(gpu_lib, problems, refs, prec):
 def test_bf16x3_gradient_gate_at_full_size(gpu_lib, problems, refs):
     _, gh = _run_batch(problems, "bf16x3")
     _grad_gate(gh, refs, "bf16x3")
+
+
+B4, SAMPLED4 = 8, 5
+
+
+@pytest.fixture(scope="module")
+def problems4():
+    return make_batch(4, B4)
+
+
+@pytest.fixture(scope="module")
+def ref4(problems4):
+    print(f"[fullsize] oracle, config 4 problem {SAMPLED4} ...", flush=True)
+    return {SAMPLED4: oracle.grape_ref(problems4[SAMPLED4])}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_config4_batch_of_8(gpu_lib, problems4, ref4, prec):
+    Fh, gh = _run_batch(problems4, prec)
+    ftol, _, rel = TOL[prec]
+    ref = ref4[SAMPLED4]
+    assert abs(Fh[SAMPLED4] - ref["F"]) <= (ftol * ref["F"] if rel else ftol), (Fh[SAMPLED4], ref["F"])
+    _grad_gate(gh, ref4, prec)
+    _properties(problems4, Fh, gh)
