@@ -60,3 +60,15 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stdout + r.stderr
     assert '"metric"' not in r.stdout
+
+
+def test_gradient_error_is_taken_per_problem():
+    """A small-gradient problem's error counts against its own scale, not the
+    batch's largest gradient."""
+    import torch
+
+    ref = torch.tensor([[[1.0, -2.0]], [[1e-3, 0.0]]], dtype=torch.float64)
+    got = ref.clone()
+    got[0, 0, 1] += 2e-6   # 1e-6 of problem 0's scale
+    got[1, 0, 0] += 1e-7   # 1e-4 of problem 1's scale, 5e-8 of the batch's
+    assert abs(bench.worst_rel_grad_err(got, ref) - 1e-4) < 1e-12
