@@ -95,7 +95,7 @@ def time_runner(qoc, torch, runner, batch, steps, warmup):
     lat = {"p50_ms": round(float(np.percentile(per, 50)), 4), "p99_ms": round(float(np.percentile(per, 99)), 4),
            "mean_ms": round(float(per.mean()), 4)}
     return {"ms_per_step": ms, "wall_s": wall, "stages": stages, "F": F.cpu().numpy(), "grad": grad,
-            "latency": lat}
+            "step_time": lat}
 
 
 def measured_traffic(kernel_avg_ms):
@@ -115,6 +115,34 @@ def measured_traffic(kernel_avg_ms):
     if hashlib.sha256(src).hexdigest() != z.get("csrc_sha256"):
         return None
     return (z["fetch_kib"] * z["fetch_scale"] + z["write_kib"] * z["write_scale"]) * 1024.0
+
+
+def serving_leg(n_requests):
+    """Request latency through the continuous-batching engine: the serving
+    workload (d from {2, ..., 128} with its weights, N ~ U{100..2000},
+    2 log2(d) controls, FP32, seeded trace 5) offered all at once to measure
+    capacity, then replayed with Poisson arrivals at 70% of that capacity,
+    batched and again one request at a time on the same arrival times."""
+    from paper_2208_12187_amd import serve
+
+    t0 = time.perf_counter()
+    trace, problems = serve.build_requests(n_requests, 5)
+    n = len(problems)
+    print(f"[bench] serving: built {n} requests in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    cap = serve.replay(problems, np.zeros(n), "fp32", 256)
+    rate = 0.7 * cap["requests_per_s"]
+    arr = serve.poisson_arrivals(n, rate, 5)
+    mix = serve.replay(problems, arr, "fp32", 256)
+    print(f"[bench] serving: batched replay done ({mix['makespan']:.1f} s)", file=sys.stderr, flush=True)
+    alone = serve.replay(problems, arr, "fp32", 1)
+    print(f"[bench] serving: one-at-a-time replay done ({alone['makespan']:.1f} s)", file=sys.stderr, flush=True)
+    return {"requests": n, "precision": "fp32", "trace_seed": 5,
+            "capacity_req_per_s": round(cap["requests_per_s"], 1),
+            "capacity_slice_steps_per_s": round(cap["slice_steps_per_s"], 1),
+            "arrival_rate_req_per_s": round(rate, 1), "load": 0.7,
+            "batched": serve.summary(mix), "one_at_a_time": serve.summary(alone),
+            "max_abs_dF_batched_vs_alone": float(np.max(np.abs(mix["F"] - alone["F"]))),
+            "per_d": {"batched": serve.per_d(mix, problems), "one_at_a_time": serve.per_d(alone, problems)}}
 
 
 def cpu_baseline():
@@ -167,6 +195,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
     ap.add_argument("--no-dense", action="store_true", help="skip the leg with the dense control kernels forced")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-engine trace replay")
+    ap.add_argument("--serving-requests", type=int, default=4096,
+                    help="requests in the serving trace (Poisson arrivals at 70%% of measured capacity)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="before timing, run one plain device-to-device copy of this many GiB "
                          "(a reference of known size for hardware byte counters)")
@@ -218,6 +249,10 @@ def main():
                                                           and B == 32) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None if traffic is None else round(traffic),
+                "traffic_source": None if traffic is None else
+                ("stored rocprofv3 reading (profiles/k_adjoint_counters.json: FETCH_SIZE + WRITE_SIZE per "
+                 "dispatch, each scaled by its reading for a plain 1 GiB copy), used because its kernel-source "
+                 "hash matches this build; not measured in this run"),
                 "kernel": "k_adjoint", "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4),
                 "cgemm_8d3_tflops": round(flops[args.precision]["adjoint_8d3"] / adj_avg_s / 1e12, 2)}
 
@@ -265,14 +300,14 @@ def main():
         b1 = qoc.Batch(batch.H0[:1], batch.Hc[:1], batch.u[:1], batch.dt, batch.V[:1])
         one = leg(args.precision, args.steps, 1, b1)
         extra["batch1"] = {"value": round(N / (one["ms_per_step"] / 1e3), 1),
-                           "ms_per_step": round(one["ms_per_step"], 3), "latency": one["latency"]}
+                           "ms_per_step": round(one["ms_per_step"], 3), "step_time": one["step_time"]}
         for pr in ("fp64", "bf16x3"):
             if pr == args.precision or (pr == "fp64" and args.no_fp64) or \
                     (pr == "bf16x3" and (args.no_bf16 or not 16 < d <= 64)):
                 continue
             o = leg(pr, args.steps, 1, b1)
             extra["batch1"][pr] = {"value": round(N / (o["ms_per_step"] / 1e3), 1),
-                                   "ms_per_step": round(o["ms_per_step"], 3), "latency": o["latency"]}
+                                   "ms_per_step": round(o["ms_per_step"], 3), "step_time": o["step_time"]}
         # the host-pointer entry point on the same problem: device allocation,
         # host-to-device copies, the path and the copy back, per call
         p0 = problems[0]
@@ -283,6 +318,9 @@ def main():
             qoc.gradient(p0.H0, p0.Hc, p0.u, p0.dt, p0.V, args.precision)
         host_ms = (time.perf_counter() - t0) / calls * 1e3
         extra["host_api_pcie_inclusive"] = {"value": round(N / (host_ms / 1e3), 1), "ms_per_call": round(host_ms, 3)}
+
+    if not args.no_serving:
+        extra["serving"] = serving_leg(args.serving_requests)
 
     cpu = None
     if not args.no_cpu:
@@ -315,7 +353,7 @@ def main():
         "cpu_baseline": None if cpu is None else {k: (round(v, 2) if isinstance(v, float) else v)
                                                   for k, v in cpu.items()},
         "path_tflops": round(total_flops / (ms / 1e3) / 1e12, 2),
-        "latency": head["latency"],
+        "step_time": head["step_time"],
         "stages_ms": stages,
     }
     out.update(extra)
