@@ -140,6 +140,29 @@ int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                      void* workspace, size_t ws_bytes, const qoc_options* opt);
 
 /*
+ * qoc_gradient_dev without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same batch layout, outputs, options and
+ * results as qoc_gradient_dev (the same kernels on the same workspace layout),
+ * but the workspace is a static device array of QOC_NOALLOC_SCRATCH_BYTES
+ * bytes inside libqoc: one copy per GPU, looked up on the first call on that
+ * device and held until the process ends.  The call allocates no device
+ * memory.  A call whose qoc_workspace_size(B, d, m, N, opt->precision,
+ * opt->chunk, opt->hbm_budget) exceeds QOC_NOALLOC_SCRATCH_BYTES returns
+ * QOC_ERR_ARG before touching the device (a smaller batch, a smaller N or an
+ * hbm_budget can bring it under).  Every call on one GPU shares that GPU's
+ * array and keeps the last call's contents; every part of it that a kernel
+ * reads is written earlier in the same call, so nothing needs clearing
+ * between calls.  Calls that overlap on one GPU (different streams, or host
+ * threads without ordering) race on it and must not be issued.
+ */
+#define QOC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+int qoc_gradient_dev_noalloc(int B, int d, int m, int N, const void* H0, const void* Hc,
+                             const void* u, double dt, const void* V, void* F, void* grad,
+                             const qoc_options* opt);
+
+/*
  * Scaling exponent and Taylor degrees the kernels use for each slice of one
  * problem (host pointers): plan[3*k + 0] = s, plan[3*k + 1] = q (degree of
  * the exp series), plan[3*k + 2] = qb (degree of the Frechet block series).

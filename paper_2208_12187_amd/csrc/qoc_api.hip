@@ -198,6 +198,44 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   return QOC_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+
+// Workspace of qoc_gradient_dev_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  In host code its name is only a
+// host-side stand-in: kernels get the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[QOC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of scratch, or null (error set).
+void* scratch_ptr() {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    fail(QOC_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    fail(QOC_ERR_DEVICE, "device index %d beyond the %d the static scratch supports", dev, kMaxDevices);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      fail(QOC_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
 // Device buffers of a host call, freed on scope exit.
 struct DevBufs {
   std::vector<void*> ptrs;
@@ -410,6 +448,23 @@ int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                      const void* V, void* F, void* grad, void* workspace, size_t ws_bytes,
                      const qoc_options* opt) {
   return run_dev(B, d, m, N, H0, Hc, u, dt, V, F, grad, nullptr, workspace, ws_bytes, opt,
+                 qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
+}
+
+int qoc_gradient_dev_noalloc(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
+                             const void* V, void* F, void* grad, const qoc_options* opt_in) {
+  const qoc_options opt = opt_in ? *opt_in : defaults();
+  int rc = check_dims(B, d, m, N, opt.precision);
+  if (rc) return rc;
+  const size_t need = make_layout(B, d, m, N, opt.precision, opt.chunk, opt.hbm_budget).total;
+  if (need > QOC_NOALLOC_SCRATCH_BYTES)
+    return fail(QOC_ERR_ARG,
+                "the call needs %zu bytes of workspace; the static scratch holds %llu (pass a smaller batch or "
+                "N, an hbm_budget, or use qoc_gradient_dev with a workspace)",
+                need, (unsigned long long)QOC_NOALLOC_SCRATCH_BYTES);
+  void* ws = scratch_ptr();
+  if (!ws) return QOC_ERR_DEVICE;
+  return run_dev(B, d, m, N, H0, Hc, u, dt, V, F, grad, nullptr, ws, QOC_NOALLOC_SCRATCH_BYTES, &opt,
                  qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
 }
 

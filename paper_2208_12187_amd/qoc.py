@@ -40,6 +40,7 @@ EXPORTS = (
     "qoc_propagate_dev",
     "qoc_fidelity_dev",
     "qoc_gradient_dev",
+    "qoc_gradient_dev_noalloc",
     "qoc_slice_plan",
     "qoc_stage_timing",
     "qoc_stage_times",
@@ -105,6 +106,7 @@ def lib() -> ctypes.CDLL:
     L.qoc_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, sz, opt]
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
+    L.qoc_gradient_dev_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, opt]
     L.qoc_slice_plan.argtypes = [i32, i32, i32, vp, vp, vp, dbl, i32, i32, vp]
     L.qoc_stage_timing.argtypes = [i32]
     L.qoc_stage_times.argtypes = [i32, vp, vp]
@@ -126,7 +128,7 @@ def lib() -> ctypes.CDLL:
     L.qoc_last_error.restype = ctypes.c_char_p
     L.qoc_version.restype = ctypes.c_char_p
     for name in ("qoc_stage_timing", "qoc_stage_times", "qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
-                 "qoc_gradient_dev", "qoc_slice_plan"):
+                 "qoc_gradient_dev", "qoc_gradient_dev_noalloc", "qoc_slice_plan"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -322,6 +324,23 @@ class Runner:
         _check(lib().qoc_propagate_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(), b.dt,
                                        out.data_ptr(), self.ws.data_ptr(), self.ws_bytes, ctypes.byref(o)))
         return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # QOC_NOALLOC_SCRATCH_BYTES in include/qoc.h
+
+
+def gradient_noalloc(b: Batch, F, grad, precision="fp64", chunk=0, hbm_budget=0, dense_controls=False,
+                     stream=None):
+    """qoc_gradient_dev_noalloc: F [B] and grad [B, m, N] (float64 device
+    tensors, caller-allocated) with libqoc's static device scratch as the
+    workspace; no device memory is allocated by the call."""
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream(F.device)
+    o = options(precision, False, chunk, ctypes.c_void_p(st.cuda_stream), hbm_budget, dense_controls)
+    _check(lib().qoc_gradient_dev_noalloc(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(),
+                                          b.dt, b.V.data_ptr(), F.data_ptr(), grad.data_ptr(), ctypes.byref(o)))
+    return F, grad
 
 
 STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint")

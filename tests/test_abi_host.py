@@ -133,3 +133,16 @@ def test_engine_footprint_tracks_the_stored_propagators():
         assert 4 * 1000 * 128 * 128 * c < f128 < 1.2 * 4 * 1000 * 128 * 128 * c
     assert L.qoc_engine_footprint(1, 0, 1, 1) == 0
     assert L.qoc_engine_footprint(1, 129, 1, 1) == 0
+
+
+def test_noalloc_rejects_oversized_call_before_any_launch():
+    """The no-allocation entry point refuses a call whose workspace exceeds its
+    static scratch, before it looks up the scratch or touches a device."""
+    L = qoc.lib()
+    need = qoc.workspace_size(1, 64, 12, 2000, "fp32")
+    assert need > qoc.NOALLOC_SCRATCH_BYTES
+    o = qoc.options("fp32")
+    rc = L.qoc_gradient_dev_noalloc(1, 64, 12, 2000, None, None, None, 0.002, None, None, None, ctypes.byref(o))
+    assert rc == -1
+    assert "static scratch" in L.qoc_last_error().decode()
+    assert qoc.workspace_size(2, 16, 8, 1000, "fp64") <= qoc.NOALLOC_SCRATCH_BYTES
