@@ -1,4 +1,5 @@
-"""CPU FP64 oracle for piecewise-constant GRAPE (test infrastructure only).
+"""CPU FP64 oracle for piecewise-constant GRAPE, unitary and state-to-state
+(test infrastructure only).
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package. The product path (the HIP library and its Python
@@ -16,6 +17,14 @@ from .grape import (
     grape_ref,
     fidelity_ref,
 )
+from .state import (
+    forward_states,
+    backward_costates,
+    state_overlap,
+    state_dg,
+    state_gradient,
+    state_ref,
+)
 
 __all__ = [
     "slice_hamiltonians",
@@ -28,4 +37,10 @@ __all__ = [
     "gradient",
     "grape_ref",
     "fidelity_ref",
+    "forward_states",
+    "backward_costates",
+    "state_overlap",
+    "state_dg",
+    "state_gradient",
+    "state_ref",
 ]

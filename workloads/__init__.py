@@ -8,6 +8,12 @@ their inputs from it without sharing any computation.
 """
 from .spin import (
     Problem,
+    StateProblem,
+    haar_state,
+    basis_state,
+    make_state,
+    make_state_batch,
+    make_state_random,
     pauli,
     site_op,
     heisenberg_drift,
@@ -28,6 +34,12 @@ from .spin import (
 
 __all__ = [
     "Problem",
+    "StateProblem",
+    "haar_state",
+    "basis_state",
+    "make_state",
+    "make_state_batch",
+    "make_state_random",
     "pauli",
     "site_op",
     "heisenberg_drift",

@@ -62,6 +62,42 @@ class Problem:
                        np.ascontiguousarray(V, dtype=np.complex128), self.name, dict(self.meta))
 
 
+@dataclass
+class StateProblem:
+    """One state-to-state GRAPE evaluation: drift H0, controls Hc[j],
+    amplitudes u[j, k], slice length dt, initial state psi0 and target state
+    chi (unit vectors of length d; complex128 / float64, row-major)."""
+
+    H0: np.ndarray
+    Hc: np.ndarray
+    u: np.ndarray
+    dt: float
+    psi0: np.ndarray
+    chi: np.ndarray
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def d(self) -> int:
+        return int(self.H0.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.Hc.shape[0])
+
+    @property
+    def N(self) -> int:
+        return int(self.u.shape[1])
+
+    def with_u(self, u: np.ndarray) -> "StateProblem":
+        return StateProblem(self.H0, self.Hc, np.ascontiguousarray(u, dtype=np.float64), self.dt,
+                            self.psi0, self.chi, self.name, dict(self.meta))
+
+    def with_target(self, chi: np.ndarray) -> "StateProblem":
+        return StateProblem(self.H0, self.Hc, self.u, self.dt, self.psi0,
+                            np.ascontiguousarray(chi, dtype=np.complex128), self.name, dict(self.meta))
+
+
 def pauli(a: str) -> np.ndarray:
     return _PAULI[a].copy()
 
@@ -162,6 +198,50 @@ def make_config(i: int, copy: Optional[int] = None, N: Optional[int] = None) -> 
     if i == 4:
         return _heisenberg_problem(7, 1000 if N is None else N, 0.005, rng, tag)
     raise ValueError(f"unknown configuration {i}")
+
+
+def haar_state(d: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed unit vector of length d: a complex Gaussian vector
+    normalised."""
+    z = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    return np.ascontiguousarray(z / np.linalg.norm(z))
+
+
+def basis_state(d: int, a: int = 0) -> np.ndarray:
+    e = np.zeros(d, dtype=np.complex128)
+    e[a] = 1.0
+    return e
+
+
+def make_state(i: int, copy: Optional[int] = None, N: Optional[int] = None) -> StateProblem:
+    """State-to-state transfer on the drift, controls, amplitudes and dt of
+    configuration i (make_config(i, copy, N)), from psi0 = |0...0> (the first
+    basis vector).  The target is chi = X|0> = |1> for configuration 1 and a
+    Haar-random state otherwise, drawn with SeedSequence([i, copy or 0, 2])."""
+    p = make_config(i, copy, N)
+    psi0 = basis_state(p.d)
+    if i == 1:
+        chi = basis_state(2, 1)
+    else:
+        chi = haar_state(p.d, np.random.default_rng(np.random.SeedSequence([i, 0 if copy is None else copy, 2])))
+    return StateProblem(p.H0, p.Hc, p.u, p.dt, psi0, chi, "state-" + p.name, dict(p.meta))
+
+
+def make_state_batch(i: int, B: int, N: Optional[int] = None) -> List[StateProblem]:
+    """B independent state-transfer draws of configuration i (copies 1..B)."""
+    return [make_state(i, copy=b + 1, N=N) for b in range(B)]
+
+
+def make_state_random(seed: int, d: int, m: int, N: int, dt: float, monomial: bool = False,
+                      u_scale: float = 0.5) -> StateProblem:
+    """State transfer with the drift, controls and amplitudes of
+    make_random (or make_random_monomial) and Haar-random psi0 and chi, drawn
+    with SeedSequence([seed, d, m, N, 3]) in the order psi0, chi."""
+    p = (make_random_monomial if monomial else make_random)(seed, d, m, N, dt, u_scale)
+    rng = np.random.default_rng(np.random.SeedSequence([seed, d, m, N, 3]))
+    psi0 = haar_state(d, rng)
+    chi = haar_state(d, rng)
+    return StateProblem(p.H0, p.Hc, p.u, dt, psi0, chi, "state-" + p.name)
 
 
 def make_batch(i: int, B: int, N: Optional[int] = None) -> List[Problem]:
