@@ -1,12 +1,13 @@
 """CPU FP64 oracle for piecewise-constant GRAPE, unitary and state-to-state,
-and for the trust-region method on the GRAPE residual (oracle.trm)
+open-system (Lindblad) GRAPE in Liouville space (oracle.lindblad) and the
+trust-region method on the GRAPE residual (oracle.trm)
 (test infrastructure only).
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package. The product path (the HIP library and its Python
 binding) never imports, calls or links anything here.
 """
-from . import trm
+from . import lindblad, trm
 from .grape import (
     slice_hamiltonians,
     expm_herm,

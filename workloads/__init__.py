@@ -9,6 +9,8 @@ their inputs from it without sharing any computation.
 from .spin import (
     Problem,
     StateProblem,
+    LindbladProblem,
+    make_lindblad,
     haar_state,
     basis_state,
     make_state,
@@ -35,6 +37,8 @@ from .spin import (
 __all__ = [
     "Problem",
     "StateProblem",
+    "LindbladProblem",
+    "make_lindblad",
     "haar_state",
     "basis_state",
     "make_state",

@@ -98,6 +98,37 @@ class StateProblem:
                             np.ascontiguousarray(chi, dtype=np.complex128), self.name, dict(self.meta))
 
 
+@dataclass
+class LindbladProblem:
+    """One open-system GRAPE evaluation: drift H0, controls Hc[j], collapse
+    operators Ls[l] (rates folded in: L = sqrt(gamma) A), amplitudes u[j, k],
+    slice length dt and the target unitary V (d x d)."""
+
+    H0: np.ndarray
+    Hc: np.ndarray
+    Ls: List[np.ndarray]
+    u: np.ndarray
+    dt: float
+    V: np.ndarray
+    name: str = ""
+
+    @property
+    def d(self) -> int:
+        return int(self.H0.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.Hc.shape[0])
+
+    @property
+    def N(self) -> int:
+        return int(self.u.shape[1])
+
+    def with_u(self, u: np.ndarray) -> "LindbladProblem":
+        return LindbladProblem(self.H0, self.Hc, self.Ls, np.ascontiguousarray(u, dtype=np.float64), self.dt,
+                               self.V, self.name)
+
+
 def pauli(a: str) -> np.ndarray:
     return _PAULI[a].copy()
 
@@ -242,6 +273,35 @@ def make_state_random(seed: int, d: int, m: int, N: int, dt: float, monomial: bo
     psi0 = haar_state(d, rng)
     chi = haar_state(d, rng)
     return StateProblem(p.H0, p.Hc, p.u, dt, psi0, chi, "state-" + p.name)
+
+
+def make_lindblad(nq: int, N: int, dt: float = 0.02, gamma_damp: float = 0.05, gamma_deph: float = 0.02,
+                  seed: int = 0) -> LindbladProblem:
+    """Open Heisenberg chain on nq qubits (J ~ U[0.5, 1.5], h ~ N(0, 0.2) as in
+    configuration 2), X/Y controls on every qubit, u ~ N(0, 0.5), a Haar
+    target, and on every qubit amplitude damping sqrt(gamma_damp) sigma_- and
+    dephasing sqrt(gamma_deph) Z (sigma_- = |0><1|).  Seeded with
+    SeedSequence([nq, N, seed, 4]), drawn in the order J, h, u, V."""
+    rng = np.random.default_rng(np.random.SeedSequence([nq, N, seed, 4]))
+    p = _heisenberg_problem(nq, N, dt, rng, f"lindblad{nq}.{N}.{seed}") if nq > 1 else None
+    if p is None:
+        H0 = rng.normal(0.0, 0.2) * pauli("z")
+        Hc = xy_controls(1)
+        u = rng.normal(0.0, 0.5, size=(2, N))
+        V = haar_unitary(2, rng)
+    else:
+        H0, Hc, u, V = p.H0, p.Hc, p.u, p.V
+    lower = np.array([[0, 1], [0, 0]], dtype=np.complex128)
+    Ls = []
+    for i in range(nq):
+        op = np.ones((1, 1), dtype=np.complex128)
+        for q in range(nq):
+            op = np.kron(op, lower if q == i else np.eye(2, dtype=np.complex128))
+        if gamma_damp > 0:
+            Ls.append(np.sqrt(gamma_damp) * op)
+        if gamma_deph > 0:
+            Ls.append(np.sqrt(gamma_deph) * site_op(i, "z", nq))
+    return LindbladProblem(H0, Hc, Ls, u, dt, V, f"lindblad{nq}.{N}.{seed}")
 
 
 def make_batch(i: int, B: int, N: Optional[int] = None) -> List[Problem]:
