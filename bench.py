@@ -145,6 +145,121 @@ def serving_leg(n_requests):
             "per_d": {"batched": serve.per_d(mix, problems), "one_at_a_time": serve.per_d(alone, problems)}}
 
 
+def state_flops(plan, d, m):
+    """VALU flops per slice of the state gradient kernel (row-table controls):
+    2 Qp matrix-vector products of H0 (8 d^2 each) with the control terms
+    (8 m d each), Qp = max(q, qb - 1), and the bilinear forms a_i^dag Hc[j] b_l
+    (per control and row about 2 qb (qb + 1) + 16 qb)."""
+    q, qb = plan[:, 1].astype(np.float64), plan[:, 2].astype(np.float64)
+    Qp = np.maximum(q, qb - 1)
+    return float((2 * Qp * (8.0 * d * d + 8.0 * m * d) + m * d * (2 * qb * (qb + 1) + 16 * qb)).sum())
+
+
+def state_leg(qoc, torch, steps, warmup, B=32):
+    """State-to-state transfer on the configuration-3 system (d = 64, m = 12,
+    N = 2000): |0...0> to a Haar state, a batch of B, FP32 and FP64."""
+    from workloads import make_state_batch
+
+    probs = make_state_batch(3, B)
+    p0 = probs[0]
+    batch = qoc.StateBatch.from_problems(probs)
+    out = {"workload": f"6-qubit Ising chain state transfer, d={p0.d}, m={p0.m}, N={p0.N}, batch of {B}"}
+    F = torch.empty(B, dtype=torch.float64, device="cuda")
+    grad = torch.empty((B, p0.m, p0.N), dtype=torch.float64, device="cuda")
+    res = {}
+    for prec in ("fp32", "fp64"):
+        r = qoc.StateRunner(B, p0.d, p0.m, p0.N, prec)
+        for _ in range(warmup):
+            r.gradient(batch, F, grad)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            r.gradient(batch, F, grad)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        qoc.stage_times()
+        qoc.stage_timing(True)
+        for _ in range(steps):
+            r.gradient(batch, F, grad)
+        torch.cuda.synchronize()
+        qoc.stage_timing(False)
+        st = qoc.stage_times()
+        plan = np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, prec, True) for p in probs])
+        g_ms = st["state_grad"][0] / max(st["state_grad"][1], 1)
+        fl = state_flops(plan, p0.d, p0.m)
+        res[prec] = (F.cpu().numpy().copy(), grad.cpu().numpy().copy())
+        out[prec] = {"value": round(B * p0.N / (ms / 1e3), 1), "unit": "slice-steps/s", "ms_per_step": round(ms, 4),
+                     "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items() if v[1]},
+                     "state_grad_roofline": {"bound": "alu", "achieved": round(fl / (g_ms / 1e3) / 1e12, 2),
+                                             "peak": 78.6, "unit": "TFLOP/s",
+                                             "frac": round(fl / (g_ms / 1e3) / 1e12 / 78.6, 4)}}
+        del r
+    (F32, g32), (F64, g64) = res["fp32"], res["fp64"]
+    out["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(F32 - F64)))
+    out["grad_err_fp32_vs_fp64"] = float(np.max(np.abs(g32 - g64).reshape(B, -1).max(1)
+                                                / np.abs(g64).reshape(B, -1).max(1)))
+    return out
+
+
+def lindblad_leg(qoc, torch, steps, warmup, B=16, nq=3, N=1000):
+    """Open-system GRAPE (general generators in Liouville space): B open
+    Heisenberg chains of nq qubits with amplitude damping and dephasing on every
+    qubit, Liouville dimension 4^nq, N slices, FP32 and FP64."""
+    from paper_2208_12187_amd import lindblad
+    from workloads import make_lindblad
+
+    probs = [make_lindblad(nq, N, dt=0.02, seed=b) for b in range(B)]
+    Gs = [lindblad.liouvillian(p.H0, p.Hc, p.Ls) for p in probs]
+    c128 = lambda xs: torch.from_numpy(np.stack(xs)).to("cuda")
+    batch = qoc.Batch(c128([g[0] for g in Gs]), c128([g[1] for g in Gs]),
+                      torch.from_numpy(np.stack([p.u for p in probs])).to("cuda"), probs[0].dt,
+                      c128([lindblad.target_superoperator(p.V) for p in probs]))
+    D, m = batch.d, batch.m
+    out = {"workload": f"{nq}-qubit open Heisenberg chain (damping + dephasing), Liouville d={D}, m={m}, N={N}, "
+                       f"batch of {B}"}
+    F = torch.empty(B, dtype=torch.float64, device="cuda")
+    grad = torch.empty((B, m, N), dtype=torch.float64, device="cuda")
+    res = {}
+    for prec in ("fp32", "fp64"):
+        r = qoc.Runner(B, D, m, N, prec, generators=True)
+        for _ in range(warmup):
+            r.gradient(batch, F, grad)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            r.gradient(batch, F, grad)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[prec] = (F.cpu().numpy().copy(), grad.cpu().numpy().copy())
+        out[prec] = {"value": round(B * N / (ms / 1e3), 1), "unit": "slice-steps/s", "ms_per_step": round(ms, 4)}
+        del r
+    (F32, g32), (F64, g64) = res["fp32"], res["fp64"]
+    out["max_abs_dF_fp32_vs_fp64"] = float(np.max(np.abs(F32 - F64)))
+    out["grad_err_fp32_vs_fp64"] = float(np.max(np.abs(g32 - g64).reshape(B, -1).max(1)
+                                                / np.abs(g64).reshape(B, -1).max(1)))
+    return out
+
+
+def trm_leg(max_iter=20):
+    """The paper's trust-region method on the GRAPE residual of configuration
+    2 (d = 16, m = 8, N = 1000: 512 residuals, 8001 parameters), FP64."""
+    from paper_2208_12187_amd import trm
+    from workloads import make_config
+
+    p = make_config(2)
+    _, _, info = trm.trm_grape(p, "fp64", max_iter=max_iter)
+    it = len(info["steps"])
+    return {"workload": "4-qubit Heisenberg chain, d=16, m=8, N=1000, FP64; residual 2 d^2 = 512, parameters m N + 1",
+            "iterations": it, "accepted": sum(1 for s in info["steps"] if s[3]), "reason": info["reason"],
+            "F_start": info["F"][0], "F_end": info["F"][-1], "seconds": round(info["seconds"], 3),
+            "jacobian_s": round(info["jac_s"], 3), "svd_s": round(info["svd_s"], 3),
+            "ms_per_iteration": round(1e3 * info["seconds"] / max(it, 1), 2)}
+
+
 def cpu_baseline():
     """The CPU oracle on one full configuration-3 problem (N = 2000 slices,
     the first problem of the benchmark batch), with the BLAS thread pools at
@@ -196,6 +311,9 @@ def main():
     ap.add_argument("--no-b1", action="store_true", help="skip the single-problem leg")
     ap.add_argument("--no-dense", action="store_true", help="skip the leg with the dense control kernels forced")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-engine trace replay")
+    ap.add_argument("--no-state", action="store_true", help="skip the state-to-state leg")
+    ap.add_argument("--no-lindblad", action="store_true", help="skip the open-system (Lindblad) leg")
+    ap.add_argument("--no-trm", action="store_true", help="skip the trust-region fit leg")
     ap.add_argument("--serving-requests", type=int, default=4096,
                     help="requests in the serving trace (Poisson arrivals at 70%% of measured capacity)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -321,6 +439,15 @@ def main():
 
     if not args.no_serving:
         extra["serving"] = serving_leg(args.serving_requests)
+    if not args.no_state:
+        extra["state_transfer"] = state_leg(qoc, torch, args.steps, args.warmup)
+        print("[bench] state-transfer leg done", file=sys.stderr, flush=True)
+    if not args.no_lindblad:
+        extra["lindblad"] = lindblad_leg(qoc, torch, args.steps, args.warmup)
+        print("[bench] Lindblad leg done", file=sys.stderr, flush=True)
+    if not args.no_trm:
+        extra["trm"] = trm_leg()
+        print("[bench] trust-region leg done", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:

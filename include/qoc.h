@@ -49,7 +49,9 @@ typedef enum {
   QOC_ERR_NONFINITE = -3,     /* validate != 0 and an input holds NaN or Inf */
   QOC_ERR_OOM = -4,           /* device allocation failed (host entry points) */
   QOC_ERR_DEVICE = -5,        /* a HIP runtime call or kernel launch failed */
-  QOC_ERR_UNSUPPORTED = -6    /* d > 128 or an unknown precision */
+  QOC_ERR_UNSUPPORTED = -6,   /* d > 128 or an unknown precision */
+  QOC_ERR_NOT_UNITARY = -7    /* validate != 0 and |V^dag V - I|_max > 1e-8, or a state
+                                 whose norm differs from 1 by more than 1e-8 */
 } qoc_status;
 
 typedef enum {
@@ -62,7 +64,13 @@ typedef enum {
 
 typedef struct {
   int32_t precision;      /* qoc_precision; default QOC_FP64 */
-  int32_t validate;       /* nonzero: host entry points check Hermiticity and finiteness */
+  int32_t validate;       /* nonzero: host entry points (no _dev suffix) check that every
+                             input is finite, that H0 and each Hc[j] are Hermitian
+                             (|H - H^dag|_max <= 1e-12 max(1, |H|_max)) and that V is
+                             unitary (|V^dag V - I|_max <= 1e-8), before any device
+                             work.  The _dev entry points never read their inputs on
+                             the host and ignore it: a non-Hermitian or non-finite
+                             input gives unspecified results there, never an error. */
   uint64_t hbm_budget;    /* bytes for the per-slice and per-chunk arrays of a call
                              (stored propagators, and the slice Hamiltonians
                              at d > 16); 0 = no limit.
@@ -72,8 +80,9 @@ typedef struct {
   double reunitarise_tol; /* reduced precision: every chunk product S of the
                              scans is checked in FP64, r = |S^dag S - I|_F, and gets one
                              Newton-Schulz step S (3I - S^dag S)/2 when r exceeds it.
-                             0 = default (1e-6 FP32, 1e-4 BF16X3); < 0 disables;
-                             never applied in FP64. */
+                             0 = default, 10 u sqrt(d L) with u = 2^-24 and L the
+                             slices per chunk (ten times the residual rounding leaves
+                             in a chunk product); < 0 disables; never applied in FP64. */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
   int32_t chunk;          /* slices per scan chunk; 0 = qoc_default_chunk(d, N) */
   int32_t dense_controls; /* 0 (default): when every control Hc[j] has at most one
@@ -86,6 +95,16 @@ typedef struct {
                              host memory for host calls): [0] |X_N^dag X_N - I|_F,
                              [1] largest chunk residual r, [2] number of Newton-Schulz
                              steps (integer stored as uint64 bits), [3] unused */
+  int32_t generators;     /* 0 (default): H0 and Hc[j] are Hermitian Hamiltonians and
+                             U_k = exp(-i dt H_k).  Nonzero: they are general complex
+                             generators G0, G[j] (no symmetry assumed) and the slice map is
+                             S_k = exp(dt (G0 + sum_j u[j*N + k] G[j])); X_N, g, F and the
+                             exact gradient are defined as above with U_k replaced by S_k.
+                             Open-system (Lindblad) dynamics in Liouville space is this
+                             case, with d the Liouville dimension.  The re-unitarisation
+                             check is off, validate checks finiteness only, and the
+                             unitary (qoc_propagate/fidelity/gradient[_dev], noalloc,
+                             trace) entry points take it; the state and engine ones do not. */
 } qoc_options; /* pass NULL for all defaults */
 
 /* Fill *opt with the defaults listed above. */
@@ -140,6 +159,20 @@ int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                      void* workspace, size_t ws_bytes, const qoc_options* opt);
 
 /*
+ * The complex trace and its derivative instead of F and dF/du:
+ *   g[b] = Tr(V_b^dag X_N)  (complex128),  dg[b][j][k] = d g[b] / d u[b][j][k]  (complex128),
+ * exact for the piecewise-constant model.  V need not be unitary: with V the
+ * residual R = X_N - e^{i phi} V0 of a least-squares fit, Re(dg) is J^T r for
+ * the real residual vector r = (Re vec R, Im vec R) and its Jacobian J in u;
+ * with V = e_a e_b^T it is the row d(X_N)_ab / du of that Jacobian.  Same
+ * layouts, options, workspace (qoc_workspace_size) and errors as
+ * qoc_gradient_dev; g and dg are device memory of 2 B and 2 B m N doubles.
+ */
+int qoc_trace_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                           const void* u, double dt, const void* V, void* g, void* dg,
+                           void* workspace, size_t ws_bytes, const qoc_options* opt);
+
+/*
  * qoc_gradient_dev without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same batch layout, outputs, options and
@@ -163,6 +196,45 @@ int qoc_gradient_dev_noalloc(int B, int d, int m, int N, const void* H0, const v
                              const qoc_options* opt);
 
 /*
+ * State-to-state transfer (the state form of GRAPE in Khaneja et al. 2005):
+ * the same slices act on a state instead of the identity,
+ *
+ *   psi_{k+1} = U_k psi_k  (psi_0 given),   g = <chi|psi_N> = sum_a conj(chi[a]) psi_N[a],
+ *   F = |g|^2,   grad[j*N + k] = dF/du[j*N + k]  (exact derivative of the piecewise-constant model),
+ *
+ * with psi_0 and the target chi unit vectors of d complex entries (qoc_z).
+ * No d x d propagator is formed: each slice is applied to a vector (and to
+ * the costate lam_k = U_k^dag lam_{k+1}, lam_N = chi) by a Taylor polynomial
+ * of the slice's plan (qoc_slice_plan), and the derivative is the plan's
+ * truncated Frechet series taken between the costate and the state.  FP64
+ * and FP32 only (QOC_BF16X3 returns QOC_ERR_UNSUPPORTED); opt->validate also
+ * checks |psi0| = |chi| = 1 within 1e-8 (QOC_ERR_NOT_UNITARY otherwise);
+ * chunk, hbm_budget, reunitarise_tol and diagnostics are ignored.
+ *
+ * Batched device forms: psi0 [B][d], chi [B][d], psiN [B][d] (qoc_z), F [B],
+ * grad [B][m][N], the other inputs as for qoc_gradient_dev; workspace of
+ * qoc_state_workspace_size(B, d, m, N, precision) bytes (0 for invalid sizes),
+ * 256-byte aligned, contents clobbered; calls sharing it must be ordered on
+ * one stream.  Errors as for the other entry points.
+ */
+size_t qoc_state_workspace_size(int B, int d, int m, int N, int precision);
+
+int qoc_state_propagate(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                        double dt, const qoc_z* psi0, qoc_z* psiN, const qoc_options* opt);
+
+int qoc_state_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u,
+                       double dt, const qoc_z* psi0, const qoc_z* chi, double* F, double* grad,
+                       const qoc_options* opt);
+
+int qoc_state_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                            const void* u, double dt, const void* psi0, void* psiN,
+                            void* workspace, size_t ws_bytes, const qoc_options* opt);
+
+int qoc_state_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
+                           const void* u, double dt, const void* psi0, const void* chi, void* F,
+                           void* grad, void* workspace, size_t ws_bytes, const qoc_options* opt);
+
+/*
  * Scaling exponent and Taylor degrees the kernels use for each slice of one
  * problem (host pointers): plan[3*k + 0] = s, plan[3*k + 1] = q (degree of
  * the exp series), plan[3*k + 2] = qb (degree of the Frechet block series).
@@ -181,7 +253,9 @@ int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const 
  * qoc_stage_times(n, ms, launches) waits for the recorded events, writes for
  * stages 0..n-1 the summed milliseconds and the number of timed launches, and
  * clears the record.  Stages: 0 prep, 1 plan, 2 expm, 3 scan (forward),
- * 4 carry, 5 mc, 6 bscan (backward scan), 7 adjoint (see qoc_stage_name).
+ * 4 carry, 5 mc, 6 bscan (backward scan), 7 adjoint, and for the state path
+ * 8 state_chain (state and costate propagation), 9 state_grad (see
+ * qoc_stage_name).
  * Returns QOC_OK or QOC_ERR_DEVICE.
  */
 int qoc_stage_timing(int enable);

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqoc.so")
-SOURCES = ["qoc_kernels.hip", "qoc_api.hip", "qoc_engine.hip"]
+SOURCES = ["qoc_kernels.hip", "qoc_api.hip", "qoc_engine.hip", "qoc_state.hip"]
 ARCH = "gfx950"
 
 

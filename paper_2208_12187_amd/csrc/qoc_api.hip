@@ -65,14 +65,34 @@ bool hermitian(const qoc_z* H, int d) {
   return dmax <= 1e-12 * std::max(1.0, hmax);
 }
 
-int validate_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, const qoc_z* V) {
+// |V^dag V - I|_max <= 1e-8: the fidelity |Tr(V^dag X_N)|^2 / d^2 is bounded
+// by 1 only for a unitary target.
+bool unitary(const qoc_z* V, int d) {
+  double worst = 0;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double re = a == b ? -1.0 : 0.0, im = 0.0;
+      for (int c = 0; c < d; ++c) {  // (V^dag V)_ab = sum_c conj(V_ca) V_cb
+        const qoc_z x = V[c * d + a], y = V[c * d + b];
+        re += x.re * y.re + x.im * y.im;
+        im += x.re * y.im - x.im * y.re;
+      }
+      worst = std::max(worst, std::max(fabs(re), fabs(im)));
+    }
+  return worst <= 1e-8;
+}
+
+int validate_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, const qoc_z* V,
+                  bool generators) {
   const size_t dd = (size_t)d * d;
   if (!finite_all(&H0->re, 2 * dd) || !finite_all(&Hc->re, 2 * dd * m) || !finite_all(u, (size_t)m * N) ||
       (V && !finite_all(&V->re, 2 * dd)))
     return fail(QOC_ERR_NONFINITE, "an input holds NaN or Inf");
+  if (generators) return QOC_OK;  // general generators and targets: no symmetry to check
   if (!hermitian(H0, d)) return fail(QOC_ERR_NOT_HERMITIAN, "H0 is not Hermitian");
   for (int j = 0; j < m; ++j)
     if (!hermitian(Hc + (size_t)j * dd, d)) return fail(QOC_ERR_NOT_HERMITIAN, "Hc[%d] is not Hermitian", j);
+  if (V && !unitary(V, d)) return fail(QOC_ERR_NOT_UNITARY, "V is not unitary (|V^dag V - I|_max > 1e-8)");
   return QOC_OK;
 }
 
@@ -115,7 +135,7 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
     const int c_n = std::min(Lo.G, Lo.P - c_lo);
     const int s_lo = c_lo * Lo.L;
     const int s_hi = std::min(N, (c_lo + c_n) * Lo.L);
-    return Range{s_lo, s_hi - s_lo, c_lo, c_n, s_lo};
+    return Range{s_lo, s_hi - s_lo, c_lo, c_n, s_lo, 0};
   };
   for (int c = 0; c < Lo.P; c += Lo.G) {
     const Range rg = segment(c);
@@ -126,7 +146,8 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
   if (grad) {
     run(ST_MC, all);
     for (int c = 0; c < Lo.P; c += Lo.G) {
-      const Range rg = segment(c);
+      Range rg = segment(c);
+      rg.recompute = 1;
       run(ST_EXPM, rg);
       run(ST_SCAN, rg);
       run(ST_BSCAN, rg);
@@ -137,22 +158,27 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
 }
 
 // Re-unitarisation threshold of a call: off in FP64.
-double reun_tol(const qoc_options& o) {
-  if (o.precision == QOC_FP64 || o.reunitarise_tol < 0) return -1.0;
+// The default is ten times the rounding level of a chunk product: in FP32 and
+// split BF16 the measured largest residual |S^dag S - I|_F of an L-slice chunk
+// product at dimension d is 0.6-1.0 u sqrt(d L) (u = 2^-24; split BF16 up to
+// 2.2 at d = 32) for d = 8 ... 128 and L = 8 ... 128.
+double reun_tol(const qoc_options& o, int d, int L) {
+  if (o.precision == QOC_FP64 || o.reunitarise_tol < 0 || o.generators) return -1.0;
   if (o.reunitarise_tol > 0) return o.reunitarise_tol;
-  return o.precision == QOC_BF16X3 ? 1e-4 : 1e-6;
+  return 10.0 * 0x1p-24 * sqrt((double)d * (double)L);
 }
 
 // Enqueue the path for a uniform batch whose inputs and outputs are in
 // device memory.  flags: qoc::RUN_* bits.
 int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt, const void* V,
-            void* F, void* grad, void* XN, void* ws, size_t ws_bytes, const qoc_options* opt_in, int flags) {
+            void* F, void* grad, void* XN, void* ws, size_t ws_bytes, const qoc_options* opt_in, int flags,
+            void* g_out = nullptr) {
   const qoc_options opt = opt_in ? *opt_in : defaults();
   int rc = check_dims(B, d, m, N, opt.precision);
   if (rc) return rc;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(QOC_ERR_ARG, "dt must be finite and > 0");
   if (!H0 || !Hc || !u) return fail(QOC_ERR_ARG, "H0, Hc and u must be non-null");
-  if ((flags & qoc::RUN_FID) && (!V || !F)) return fail(QOC_ERR_ARG, "V and F must be non-null");
+  if ((flags & qoc::RUN_FID) && (!V || (!F && !g_out))) return fail(QOC_ERR_ARG, "V and F must be non-null");
   if ((flags & qoc::RUN_GRAD) && !grad) return fail(QOC_ERR_ARG, "grad must be non-null");
   if (!ws) return fail(QOC_ERR_ARG, "workspace must be non-null");
   if (((uintptr_t)ws) % kAlign) return fail(QOC_ERR_ARG, "workspace must be 256-byte aligned");
@@ -163,16 +189,19 @@ int run_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const vo
   char* base = static_cast<char*>(ws);
   std::vector<ProbDesc> descs(B);
   const size_t dd = (size_t)d * d;
-  const double tol = reun_tol(opt);
+  const double tol = reun_tol(opt, d, Lo.L);
   for (int b = 0; b < B; ++b) {
     char* pb = base + Lo.desc_bytes + (size_t)b * Lo.per_prob;
-    fill_desc(descs[b], Lo, pb, d, m, N, dt, flags | (opt.dense_controls ? qoc::CTRL_DENSE : 0),
+    fill_desc(descs[b], Lo, pb, d, m, N, dt,
+              flags | (opt.dense_controls ? qoc::CTRL_DENSE : 0) | (opt.generators ? qoc::RUN_GENERAL : 0),
               static_cast<const double*>(H0) + 2 * dd * b,
               static_cast<const double*>(Hc) + 2 * dd * m * b, static_cast<const double*>(u) + (size_t)m * N * b,
               V ? static_cast<const double*>(V) + 2 * dd * b : nullptr, F ? static_cast<double*>(F) + b : nullptr,
-              grad ? static_cast<double*>(grad) + (size_t)m * N * b : nullptr,
+              // the complex dg of the trace gradient takes two doubles per entry
+              grad ? static_cast<double*>(grad) + (size_t)m * N * b * ((flags & qoc::RUN_RAWDG) ? 2 : 1) : nullptr,
               XN ? static_cast<double*>(XN) + 2 * dd * b : nullptr, tol,
               opt.diagnostics ? opt.diagnostics + 4 * b : nullptr);
+    if (g_out) descs[b].g = static_cast<double*>(g_out) + 2 * b;
   }
   hipStream_t st = static_cast<hipStream_t>(opt.stream);
   hipError_t e = hipMemcpyAsync(base, descs.data(), (size_t)B * sizeof(ProbDesc), hipMemcpyHostToDevice, st);
@@ -261,7 +290,7 @@ int run_host(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double
   if ((flags & qoc::RUN_GRAD) && !grad) return fail(QOC_ERR_ARG, "grad must be non-null");
   if (!(flags & qoc::RUN_FID) && !XN) return fail(QOC_ERR_ARG, "U_total must be non-null");
   if (opt.validate) {
-    rc = validate_host(d, m, N, H0, Hc, u, V);
+    rc = validate_host(d, m, N, H0, Hc, u, V, opt.generators != 0);
     if (rc) return rc;
   }
   const size_t dd = (size_t)d * d;
@@ -310,7 +339,7 @@ struct StageTimer {
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  hipEvent_t open[qoc::ST_COUNT] = {};
+  hipEvent_t open[qoc::ST_ALL] = {};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -389,8 +418,9 @@ int qoc_stage_times(int n, double* ms, int64_t* launches) {
 }
 
 const char* qoc_stage_name(int stage) {
-  static const char* names[] = {"prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint"};
-  return (stage >= 0 && stage < qoc::ST_COUNT) ? names[stage] : "";
+  static const char* names[] = {"prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint",
+                                "state_chain", "state_grad"};
+  return (stage >= 0 && stage < qoc::ST_ALL) ? names[stage] : "";
 }
 
 
@@ -405,6 +435,7 @@ void qoc_default_options(qoc_options* opt) {
   opt->stream = nullptr;
   opt->chunk = 0;
   opt->dense_controls = 0;
+  opt->generators = 0;
 }
 
 int qoc_propagate(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const double* u, double dt,
@@ -449,6 +480,14 @@ int qoc_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                      const qoc_options* opt) {
   return run_dev(B, d, m, N, H0, Hc, u, dt, V, F, grad, nullptr, workspace, ws_bytes, opt,
                  qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
+}
+
+int qoc_trace_gradient_dev(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,
+                           const void* V, void* g, void* dg, void* workspace, size_t ws_bytes,
+                           const qoc_options* opt) {
+  if (!g || !dg) return fail(QOC_ERR_ARG, "g and dg must be non-null");
+  return run_dev(B, d, m, N, H0, Hc, u, dt, V, nullptr, dg, nullptr, workspace, ws_bytes, opt,
+                 qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD | qoc::RUN_RAWDG, g);
 }
 
 int qoc_gradient_dev_noalloc(int B, int d, int m, int N, const void* H0, const void* Hc, const void* u, double dt,

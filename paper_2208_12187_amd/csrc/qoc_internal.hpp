@@ -51,6 +51,11 @@ struct ProbDesc {
   double* diag;       // [0] ||X_N^dag X_N - I||_F; [1] largest chunk residual (FP64
                       // bits, atomic max); [2] re-unitarisation steps (uint64 count)
   double reun_tol;    // re-unitarisation threshold for chunk totals, < 0: off
+  // state-to-state path (qoc_state_*): XN above receives psi_N (d complex128)
+  const double* psi0z;  // (user) d complex128 initial state, or null
+  const double* chiz;   // (user) d complex128 target state, or null
+  void* psi;            // N + 1 vectors of D complex T: psi_0 .. psi_N
+  void* lam;            // N + 1 vectors of D complex T: lam_0 .. lam_N
 };
 
 enum : int {
@@ -58,6 +63,8 @@ enum : int {
   RUN_GRAD = 2,  // adjoint pass and gradient
   RUN_FID = 4,   // fidelity against V
   CTRL_DENSE = 8,  // always the dense control kernels (qoc_options.dense_controls)
+  RUN_RAWDG = 16,  // write dg/du[j][k] = d Tr(V^dag X_N) / du[j][k] (complex) instead of dF/du
+  RUN_GENERAL = 32,  // H0, Hc are general generators G (stored as i G; see prep_one)
 };
 
 // A launch over many problems that share d (and hence D) and the precision.
@@ -88,14 +95,20 @@ constexpr int kScratchMats = 6;
 
 // Stages of the path, for the optional per-stage event timing.
 enum Stage : int { ST_PREP = 0, ST_PLAN, ST_EXPM, ST_SCAN, ST_CARRY, ST_MC, ST_BSCAN, ST_ADJ, ST_COUNT };
+// Stages of the state-to-state path (timed only; not part of the engine's graph).
+enum : int { ST_SCHAIN = ST_COUNT, ST_SGRAD, ST_ALL };
 void stage_mark(int stage, bool begin, hipStream_t st);
 
 // Sub-range of a uniform launch: slices [s_lo, s_lo + s_n) and chunks
 // [c_lo, c_lo + c_n) of every problem (s_n / c_n = 0: all, from the start
 // arrays); the per-slice arrays delta / xprev / bloc hold slices from kbase
-// on (checkpointed segments keep only a window of them).
+// on (checkpointed segments keep only a window of them).  recompute marks
+// the second sweep of a checkpointed call, whose forward scans only rebuild
+// the local products: their chunk totals were checked, stored and consumed by
+// the carry in the first sweep, so the re-unitarisation check is not repeated.
 struct Range {
   int s_lo, s_n, c_lo, c_n, kbase;
+  int recompute;
 };
 
 // Work items of one kernel launch.  API launches pass nprob / total / start

@@ -87,6 +87,7 @@ template <typename T, int D>
 __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const double* src) {
   const int d = P.d;
   const int a = threadIdx.x;
+  const bool gen = (P.flags & RUN_GENERAL) != 0;  // stored as i G (see prep_one)
   int multi = 0;
   {
     if (a < D) {
@@ -94,7 +95,8 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
       T vr = 0, vi = 0;
       if (a < d)
         for (int c = 0; c < d; ++c) {
-          const T r = (T)src[2 * (a * d + c)], i = (T)src[2 * (a * d + c) + 1];
+          const double sr = src[2 * (a * d + c)], si = src[2 * (a * d + c) + 1];
+          const T r = (T)(gen ? -si : sr), i = (T)(gen ? sr : si);
           if (r != (T)0 || i != (T)0) {
             ++cnt;
             col = c;
@@ -124,7 +126,11 @@ __device__ __forceinline__ bool controls_monomial(const ProbDesc& P) {
 
 // Convert the caller's complex128 matrices to the compute precision: H0 and
 // Hc[j] to planar D x D (zero padded), V to PF; also the FP64 one-norms
-// (largest column sum of moduli) of H0 and Hc[j].
+// (largest column sum of moduli) of H0 and Hc[j].  With general generators
+// (RUN_GENERAL) the caller's G is stored as H = i G, so that every kernel's
+// A = -i dt H is dt G, and the norm is the larger of the one- and
+// infinity-norms: the adjoint works with A^dag, whose one-norm is A's
+// infinity-norm.
 template <typename T, int D>
 __device__ __forceinline__ void prep_one(const ProbDesc& P, int mat, double* colmax) {
   const int d = P.d, m = P.m;
@@ -142,15 +148,29 @@ __device__ __forceinline__ void prep_one(const ProbDesc& P, int mat, double* col
         re = src[2 * (row * d + col)];
         im = src[2 * (row * d + col) + 1];
       }
+      if (P.flags & RUN_GENERAL) {  // i (re + i im)
+        const double t = re;
+        re = -im;
+        im = t;
+      }
       dst[e] = (T)re;
       dst[D * D + e] = (T)im;
     }
     double s = 0;
-    if ((int)threadIdx.x < d)
+    if ((int)threadIdx.x < d) {
       for (int row = 0; row < d; ++row) {
         double re = src[2 * (row * d + threadIdx.x)], im = src[2 * (row * d + threadIdx.x) + 1];
         s += sqrt(fma(re, re, im * im));
       }
+      if (P.flags & RUN_GENERAL) {
+        double r = 0;
+        for (int col = 0; col < d; ++col) {
+          double re = src[2 * (threadIdx.x * d + col)], im = src[2 * (threadIdx.x * d + col) + 1];
+          r += sqrt(fma(re, re, im * im));
+        }
+        s = fmax(s, r);
+      }
+    }
     colmax[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -217,7 +237,7 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
 template <typename T, int D, typename Ops, int G = 1>
 __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, double c, double sgn, T* hk,
-                                         bool mono) {
+                                         bool mono, bool ct = false) {
   // The matrix is read as D^2/4 chunks of four consecutive row elements;
   // thread t owns chunks t, t + 4D, t + 8D, ... (D/16 of them), so that the
   // lanes of one 16-byte load read consecutive chunks.  The loads of G
@@ -332,7 +352,14 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const int e = e0 + 4 * NT * v;
-    Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
+    if (ct) {
+      // (-i (-f) H)^dag = -i f H^dag (see ham_put): element (col, row) is
+      // -i f conj(H[row][col]) = -f hi - i f hr
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ops::put(lds, e % D + i, e / D, -f * hi[v][i], -f * hr[v][i]);
+    } else {
+      Ops::put4(lds, e / D, e % D, f * hi[v], -f * hr[v]);  // -i f (hr + i hi)
+    }
     if (hk) {
       Prec<T>::gst4(hk + e, hr[v]);
       Prec<T>::gst4(hk + D * D + e, hi[v]);
@@ -359,15 +386,23 @@ __device__ __forceinline__ void ham_load(HamRegs<T, D>& H, const T* hk) {
   }
 }
 
+// ct: write (-i (-sgn) c H_k)^dag instead of -i sgn c H_k.  The two agree
+// when H_k is Hermitian; for general generators the adjoint's call
+// (sgn = -1) then gets (-i c H_k)^dag = A_k^dag / 2^s.
 template <typename T, int D, typename Ops>
-__device__ __forceinline__ void ham_put(void* lds, const HamRegs<T, D>& H, double c, double sgn) {
+__device__ __forceinline__ void ham_put(void* lds, const HamRegs<T, D>& H, double c, double sgn, bool ct = false) {
   constexpr int NT = 4 * D;
   const int e0 = 4 * threadIdx.x;
   const T f = (T)(sgn * c);
 #pragma unroll
   for (int v = 0; v < D / 16; ++v) {
     const int e = e0 + 4 * NT * v;
-    Ops::put4(lds, e / D, e % D, f * H.hi[v], -f * H.hr[v]);
+    if (ct) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ops::put(lds, e % D + i, e / D, -f * H.hi[v][i], -f * H.hr[v][i]);
+    } else {
+      Ops::put4(lds, e / D, e % D, f * H.hi[v], -f * H.hr[v]);
+    }
   }
 }
 
@@ -483,8 +518,15 @@ __device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j
       a += rg[(2 * jj) * NWAVES + w];
       b += rg[(2 * jj + 1) * NWAVES + w];
     }
-    const double pref = 2.0 * P.dt / ((double)P.d * P.d);
-    gp(P.grad)[(size_t)(j0 + jj) * P.N + k] = pref * (gp(P.g)[0] * b - gp(P.g)[1] * a);
+    if (P.flags & RUN_RAWDG) {
+      // dg/du[j][k] = -i dt Tr(Z_k^dag Hc[j]), complex interleaved
+      const size_t o = 2 * ((size_t)(j0 + jj) * P.N + k);
+      gp(P.grad)[o] = P.dt * b;
+      gp(P.grad)[o + 1] = -P.dt * a;
+    } else {
+      const double pref = 2.0 * P.dt / ((double)P.d * P.d);
+      gp(P.grad)[(size_t)(j0 + jj) * P.N + k] = pref * (gp(P.g)[0] * b - gp(P.g)[1] * a);
+    }
   }
 }
 
@@ -756,7 +798,7 @@ void k_scan_local(Work W, int bwd) {
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
   }
-  if (!bwd) {
+  if (!bwd && !W.rg.recompute) {
     if constexpr (sizeof(T) == 4) {
       static_assert(2 * Ops::BYTES >= (int)sizeof(double) * Mat<double, D>::LDS_ELEMS, "LDS too small");
       if (P.reun_tol >= 0) reunitarise<D>(P, S, &lds[0][0], red, L);
@@ -964,9 +1006,10 @@ void k_adjoint(Work W) {
   Ops::store(lds[1], R2, L);
   if constexpr (kKeepH<D>) {
     if constexpr (!kEarlyH<T, D>) ham_load<T, D>(ham, pf_mat<T, D>(P.hk, k - W.rg.kbase));
-    ham_put<T, D, Ops>(lds[0], ham, ldexp(P.dt, -s), -1.0);
+    ham_put<T, D, Ops>(lds[0], ham, ldexp(P.dt, -s), -1.0, (P.flags & RUN_GENERAL) != 0);
   } else {
-    assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr, mono);
+    assemble<T, D, Ops, (sizeof(T) == 4 ? 4 : 2)>(lds[0], P, k, ldexp(P.dt, -s), -1.0, nullptr, mono,
+                                                  (P.flags & RUN_GENERAL) != 0);
   }
   __syncthreads();
   const void* X = lds[0];
@@ -1623,7 +1666,7 @@ __global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
         panel_store(k + 1 < k1 ? pf_mat<T, 128>(P.xprev, k + 1 - W.rg.kbase) : pf_mat<T, 128>(P.tf, c), acc, L);
       }
       if constexpr (sizeof(T) == 4) {
-        if (P.reun_tol >= 0)
+        if (P.reun_tol >= 0 && !W.rg.recompute)
           reunitarise128(P, pf_mat<T, 128>(P.tf, c), pf_mat<T, 128>(P.cf, c), reinterpret_cast<float*>(lds), red, L);
       }
     } else {
@@ -1767,11 +1810,17 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     panel_store(SE, acc, L);
     panel_scale(acc, (T)(1.0 / qb));
     panel_store(SR2, acc, L);
-    // X = A^dag / 2^s = -(A / 2^s), the expm pass's matrix negated (own
+    // X = A^dag / 2^s: the expm pass's A / 2^s negated (A = -i dt H_k with H_k
+    // Hermitian), or its conjugate transpose for general generators (own
     // panel; the barrier at the start of the next product publishes SX)
-    panel_load(acc, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
-    panel_scale(acc, (T)-1);
-    panel_store(SX, acc, L);
+    if (P.flags & RUN_GENERAL) {
+      transpose128<T>(SX, lds, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
+      panel_load(acc, SX, L);
+    } else {
+      panel_load(acc, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
+      panel_scale(acc, (T)-1);
+      panel_store(SX, acc, L);
+    }
     // R1 = I + X / qb
     panel_scale(acc, (T)(1.0 / qb));
     panel_add_identity(acc, L, (T)1);

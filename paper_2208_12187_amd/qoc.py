@@ -27,6 +27,7 @@ _ERRORS = {
     -4: "QOC_ERR_OOM",
     -5: "QOC_ERR_DEVICE",
     -6: "QOC_ERR_UNSUPPORTED",
+    -7: "QOC_ERR_NOT_UNITARY",
 }
 
 # Every symbol include/qoc.h declares.
@@ -41,7 +42,13 @@ EXPORTS = (
     "qoc_fidelity_dev",
     "qoc_gradient_dev",
     "qoc_gradient_dev_noalloc",
+    "qoc_trace_gradient_dev",
     "qoc_slice_plan",
+    "qoc_state_workspace_size",
+    "qoc_state_propagate",
+    "qoc_state_gradient",
+    "qoc_state_propagate_dev",
+    "qoc_state_gradient_dev",
     "qoc_stage_timing",
     "qoc_stage_times",
     "qoc_stage_name",
@@ -74,6 +81,7 @@ class Options(ctypes.Structure):
         ("chunk", ctypes.c_int32),
         ("dense_controls", ctypes.c_int32),
         ("diagnostics", ctypes.c_void_p),
+        ("generators", ctypes.c_int32),
     ]
 
 
@@ -107,7 +115,14 @@ def lib() -> ctypes.CDLL:
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, opt]
+    L.qoc_trace_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
     L.qoc_slice_plan.argtypes = [i32, i32, i32, vp, vp, vp, dbl, i32, i32, vp]
+    L.qoc_state_workspace_size.argtypes = [i32, i32, i32, i32, i32]
+    L.qoc_state_workspace_size.restype = sz
+    L.qoc_state_propagate.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, opt]
+    L.qoc_state_gradient.argtypes = [i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, opt]
+    L.qoc_state_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
+    L.qoc_state_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, vp, sz, opt]
     L.qoc_stage_timing.argtypes = [i32]
     L.qoc_stage_times.argtypes = [i32, vp, vp]
     L.qoc_stage_name.argtypes = [i32]
@@ -128,7 +143,9 @@ def lib() -> ctypes.CDLL:
     L.qoc_last_error.restype = ctypes.c_char_p
     L.qoc_version.restype = ctypes.c_char_p
     for name in ("qoc_stage_timing", "qoc_stage_times", "qoc_propagate", "qoc_fidelity", "qoc_gradient", "qoc_propagate_dev", "qoc_fidelity_dev",
-                 "qoc_gradient_dev", "qoc_gradient_dev_noalloc", "qoc_slice_plan"):
+                 "qoc_gradient_dev", "qoc_gradient_dev_noalloc", "qoc_trace_gradient_dev", "qoc_slice_plan",
+                 "qoc_state_propagate",
+                 "qoc_state_gradient", "qoc_state_propagate_dev", "qoc_state_gradient_dev"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -139,9 +156,11 @@ def _check(rc: int):
         raise QocError(rc, lib().qoc_last_error().decode())
 
 
-def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0, dense_controls=False) -> Options:
+def options(precision="fp64", validate=False, chunk=0, stream=None, hbm_budget=0, dense_controls=False,
+            generators=False) -> Options:
     o = Options()
     lib().qoc_default_options(ctypes.byref(o))
+    o.generators = 1 if generators else 0
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.validate = 1 if validate else 0
     o.chunk = int(chunk)
@@ -165,35 +184,66 @@ def _ptr(a: np.ndarray):
 
 # ------------------------------------------------------------ host entry points
 
-def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False) -> np.ndarray:
+def propagate(H0, Hc, u, dt, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False, generators=False) -> np.ndarray:
     """X_N = U_{N-1} ... U_0 (host arrays in, host array out)."""
     H0, Hc, u = _c128(H0), _c128(Hc), _f64(u)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     out = np.empty((d, d), dtype=np.complex128)
-    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls, generators)
     _check(lib().qoc_propagate(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(out), ctypes.byref(o)))
     return out
 
 
-def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False) -> float:
+def fidelity(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False, generators=False) -> float:
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
-    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls, generators)
     _check(lib().qoc_fidelity(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), ctypes.byref(o)))
     return float(F[0])
 
 
-def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False):
+def gradient(H0, Hc, u, dt, V, precision="fp64", validate=False, chunk=0, hbm_budget=0, dense_controls=False, generators=False):
     """(F, grad) with grad[j, k] = dF/du[j, k]."""
     H0, Hc, u, V = _c128(H0), _c128(Hc), _f64(u), _c128(V)
     d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
     F = np.zeros(1)
     grad = np.empty((m, N))
-    o = options(precision, validate, chunk, None, hbm_budget, dense_controls)
+    o = options(precision, validate, chunk, None, hbm_budget, dense_controls, generators)
     _check(lib().qoc_gradient(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(V), _ptr(F), _ptr(grad),
                               ctypes.byref(o)))
     return float(F[0]), grad
+
+
+def state_propagate(H0, Hc, u, dt, psi0, precision="fp64", validate=False, dense_controls=False) -> np.ndarray:
+    """psi_N = U_{N-1} ... U_0 psi0 (host arrays in, host array out)."""
+    H0, Hc, u, psi0 = _c128(H0), _c128(Hc), _f64(u), _c128(psi0)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    out = np.empty(d, dtype=np.complex128)
+    o = options(precision, validate, 0, None, 0, dense_controls)
+    _check(lib().qoc_state_propagate(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(psi0), _ptr(out),
+                                     ctypes.byref(o)))
+    return out
+
+
+def state_gradient(H0, Hc, u, dt, psi0, chi, precision="fp64", validate=False, dense_controls=False):
+    """(F, grad) of the state transfer psi0 -> chi, F = |<chi|psi_N>|^2."""
+    H0, Hc, u, psi0, chi = _c128(H0), _c128(Hc), _f64(u), _c128(psi0), _c128(chi)
+    d, m, N = H0.shape[0], Hc.shape[0], u.shape[1]
+    F = np.zeros(1)
+    grad = np.empty((m, N))
+    o = options(precision, validate, 0, None, 0, dense_controls)
+    _check(lib().qoc_state_gradient(d, m, N, _ptr(H0), _ptr(Hc), _ptr(u), float(dt), _ptr(psi0), _ptr(chi),
+                                    _ptr(F), _ptr(grad), ctypes.byref(o)))
+    return float(F[0]), grad
+
+
+def state_workspace_size(B, d, m, N, precision="fp64") -> int:
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = lib().qoc_state_workspace_size(B, d, m, N, p)
+    if n == 0:
+        _check(-1)
+    return int(n)
 
 
 def slice_plan(H0, Hc, u, dt, precision="fp64", with_gradient=True) -> np.ndarray:
@@ -264,9 +314,11 @@ class Batch:
 class Runner:
     """Owns a device workspace for repeated calls on batches of one shape."""
 
-    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda", hbm_budget=0, dense_controls=False):
+    def __init__(self, B, d, m, N, precision="fp64", chunk=0, device="cuda", hbm_budget=0, dense_controls=False,
+                 generators=False):
         import torch
 
+        self.generators = bool(generators)
         self.B, self.d, self.m, self.N = B, d, m, N
         self.precision = precision
         self.chunk = chunk
@@ -281,7 +333,7 @@ class Runner:
 
         st = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
         return options(self.precision, False, self.chunk, ctypes.c_void_p(st.cuda_stream), self.hbm_budget,
-                       self.dense_controls)
+                       self.dense_controls, self.generators)
 
     def _shape_ok(self, b: Batch):
         if (b.B, b.d, b.m, b.N) != (self.B, self.d, self.m, self.N):
@@ -301,6 +353,22 @@ class Runner:
                                       b.V.data_ptr(), F.data_ptr(), grad.data_ptr(), self.ws.data_ptr(),
                                       self.ws_bytes, ctypes.byref(o)))
         return F, grad
+
+    def trace_gradient(self, b: Batch, g=None, dg=None, stream=None):
+        """Enqueue g [B] = Tr(V^dag X_N) and dg [B, m, N] = dg/du (complex128
+        device tensors); V need not be unitary."""
+        import torch
+
+        self._shape_ok(b)
+        if g is None:
+            g = torch.empty(b.B, dtype=torch.complex128, device=self.ws.device)
+        if dg is None:
+            dg = torch.empty((b.B, b.m, b.N), dtype=torch.complex128, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_trace_gradient_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(),
+                                            b.dt, b.V.data_ptr(), g.data_ptr(), dg.data_ptr(), self.ws.data_ptr(),
+                                            self.ws_bytes, ctypes.byref(o)))
+        return g, dg
 
     def fidelity(self, b: Batch, F=None, stream=None):
         import torch
@@ -326,6 +394,78 @@ class Runner:
         return out
 
 
+class StateBatch:
+    """B state-transfer problems with shared (d, m, N, dt) on a torch device:
+    H0 [B, d, d], Hc [B, m, d, d] complex128, u [B, m, N] float64,
+    psi0 [B, d], chi [B, d] complex128."""
+
+    def __init__(self, H0, Hc, u, dt, psi0, chi):
+        import torch
+
+        self.H0, self.Hc, self.u = H0.contiguous(), Hc.contiguous(), u.contiguous()
+        self.psi0, self.chi = psi0.contiguous(), chi.contiguous()
+        self.dt = float(dt)
+        self.B, self.d = self.H0.shape[0], self.H0.shape[1]
+        self.m, self.N = self.u.shape[1], self.u.shape[2]
+        assert self.H0.dtype == torch.complex128 and self.psi0.dtype == torch.complex128
+        assert tuple(self.psi0.shape) == (self.B, self.d) and tuple(self.chi.shape) == (self.B, self.d)
+        assert tuple(self.Hc.shape) == (self.B, self.m, self.d, self.d)
+
+    @staticmethod
+    def from_problems(problems, device="cuda"):
+        import torch
+
+        st = lambda xs: torch.from_numpy(np.stack(xs)).to(device)
+        dts = {p.dt for p in problems}
+        assert len(dts) == 1, "a batch shares dt"
+        return StateBatch(st([p.H0 for p in problems]), st([p.Hc for p in problems]), st([p.u for p in problems]),
+                          dts.pop(), st([p.psi0 for p in problems]), st([p.chi for p in problems]))
+
+
+class StateRunner:
+    """Owns a device workspace for repeated state-transfer calls of one shape."""
+
+    def __init__(self, B, d, m, N, precision="fp64", device="cuda", dense_controls=False):
+        import torch
+
+        self.B, self.d, self.m, self.N, self.precision = B, d, m, N, precision
+        self.dense_controls = bool(dense_controls)
+        self.ws_bytes = state_workspace_size(B, d, m, N, precision)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+
+    def _opt(self, stream):
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream(self.ws.device)
+        return options(self.precision, False, 0, ctypes.c_void_p(st.cuda_stream), 0, self.dense_controls)
+
+    def gradient(self, b: StateBatch, F=None, grad=None, stream=None):
+        import torch
+
+        if (b.B, b.d, b.m, b.N) != (self.B, self.d, self.m, self.N):
+            raise ValueError("batch shape does not match the runner")
+        if F is None:
+            F = torch.empty(b.B, dtype=torch.float64, device=self.ws.device)
+        if grad is None:
+            grad = torch.empty((b.B, b.m, b.N), dtype=torch.float64, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_state_gradient_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(),
+                                            b.dt, b.psi0.data_ptr(), b.chi.data_ptr(), F.data_ptr(),
+                                            grad.data_ptr(), self.ws.data_ptr(), self.ws_bytes, ctypes.byref(o)))
+        return F, grad
+
+    def propagate(self, b: StateBatch, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty((b.B, b.d), dtype=torch.complex128, device=self.ws.device)
+        o = self._opt(stream)
+        _check(lib().qoc_state_propagate_dev(b.B, b.d, b.m, b.N, b.H0.data_ptr(), b.Hc.data_ptr(), b.u.data_ptr(),
+                                             b.dt, b.psi0.data_ptr(), out.data_ptr(), self.ws.data_ptr(),
+                                             self.ws_bytes, ctypes.byref(o)))
+        return out
+
+
 NOALLOC_SCRATCH_BYTES = 64 << 20  # QOC_NOALLOC_SCRATCH_BYTES in include/qoc.h
 
 
@@ -343,7 +483,7 @@ def gradient_noalloc(b: Batch, F, grad, precision="fp64", chunk=0, hbm_budget=0,
     return F, grad
 
 
-STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint")
+STAGES = ("prep", "plan", "expm", "scan", "carry", "mc", "bscan", "adjoint", "state_chain", "state_grad")
 
 
 class Engine:

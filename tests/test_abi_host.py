@@ -56,6 +56,10 @@ def test_argument_errors_before_any_launch():
     u[2, 5] = np.inf
     assert _err(qoc.gradient, p.H0, p.Hc, u, p.dt, p.V, "fp64", True) == -3
     assert _err(qoc.gradient, p.H0, p.Hc, p.u, p.dt, p.V, 7) == -6      # unknown precision
+    assert _err(qoc.gradient, p.H0, p.Hc, p.u, p.dt, 1.001 * p.V, "fp64", True) == -7   # V not unitary
+    Vp = p.V.copy()
+    Vp[:, [0, 1]] = Vp[:, [1, 0]]                                        # still unitary: passes the check
+    assert _err(qoc.gradient, p.H0, bad, p.u, p.dt, Vp, "fp64", True) == -2
     assert _err(qoc.gradient, p.H0, p.Hc, p.u[:, :0], p.dt, p.V) == -1   # no slices
     assert _err(qoc.gradient, p.H0, p.Hc[:0], p.u[:0], p.dt, p.V) == -1  # no controls
     assert _err(qoc.fidelity, p.H0, p.Hc, p.u[:, :0], p.dt, p.V) == -1

@@ -116,7 +116,7 @@ def test_differentiation_workload_full_size(gpu_lib):
         assert abs(fd - grad[j, k]) <= 1e-4 * max(abs(grad[j, k]), 0.1 * gmax), (j, k, fd, grad[j, k])
 
 
-def _grad_diag(p, prec, tol):
+def _grad_diag(p, prec, tol, hbm_budget=0):
     """Host-entry gradient with the diagnostics block returned."""
     import ctypes
     from paper_2208_12187_amd import qoc
@@ -125,7 +125,7 @@ def _grad_diag(p, prec, tol):
     F = np.zeros(1)
     grad = np.empty((p.m, p.N))
     diag = np.zeros(4)
-    o = qoc.options(prec)
+    o = qoc.options(prec, hbm_budget=hbm_budget)
     o.reunitarise_tol = tol
     o.diagnostics = diag.ctypes.data
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
@@ -152,9 +152,18 @@ def test_reunitarisation_check_and_step(gpu_lib, cfg, N, prec):
     L = qoc.default_chunk(p.d, p.N)
     P = -(-p.N // L)
     assert n0 == 0 and rmax0 == 0.0
-    assert 0 < rmax1 < 1e-3
+    # the default threshold, 10 u sqrt(d L), sits above the rounding residual
+    # of a well-conditioned chunk product: no step is taken by default
+    assert 0 < rmax1 < 10 * 2.0 ** -24 * np.sqrt(p.d * L) and n1 == 0
     assert n2 == P  # one step per forward chunk total (the backward totals are their adjoints)
     assert rX2 <= 2 * rX0 + 1e-12
+    # checkpointed: the second sweep rebuilds the local products without
+    # checking the chunk totals again, so the counts and the results stay those
+    # of the unsegmented call
+    budget = qoc.workspace_size(1, p.d, p.m, p.N, prec) // 3
+    F3, g3, rX3, rmax3, n3 = _grad_diag(p, prec, 1e-14, hbm_budget=budget)
+    assert n3 == P and rmax3 == rmax2
+    assert F3 == F2 and np.array_equal(g3, g2)
     gmax = np.max(np.abs(ref["grad"]))
     for F, g in ((F0, g0), (F1, g1), (F2, g2)):
         assert abs(F - ref["F"]) <= 1e-5

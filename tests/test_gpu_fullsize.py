@@ -135,3 +135,31 @@ def test_config4_batch_of_8(gpu_lib, problems4, ref4, prec):
     assert abs(Fh[SAMPLED4] - ref["F"]) <= (ftol * ref["F"] if rel else ftol), (Fh[SAMPLED4], ref["F"])
     _grad_gate(gh, ref4, prec)
     _properties(problems4, Fh, gh)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config2_at_full_size(gpu_lib, prec):
+    """Configuration 2 (4-qubit Heisenberg chain, d = 16, m = 8, N = 1000,
+    dt = 0.005) at its own size: FP32 rounding accumulates over the whole
+    1000-slice chain, so both precisions are gated against the oracle here,
+    over a batch of 4 seeded copies through one Runner."""
+    import torch
+    from paper_2208_12187_amd import qoc
+
+    probs = make_batch(2, 4)
+    assert probs[0].N == 1000 and probs[0].d == 16
+    print(f"[fullsize] configuration 2, batch 4, {prec}", flush=True)
+    batch = qoc.Batch.from_problems(probs)
+    runner = qoc.Runner(4, 16, 8, 1000, prec)
+    F, grad = runner.gradient(batch)
+    torch.cuda.synchronize()
+    F, grad = F.cpu().numpy(), grad.cpu().numpy()
+    ftol, gtol, rel = TOL[prec]
+    for b, p in enumerate(probs):
+        ref = oracle.grape_ref(p)
+        assert abs(F[b] - ref["F"]) <= (ftol * ref["F"] if rel else ftol), (b, F[b], ref["F"])
+        gmax = np.max(np.abs(ref["grad"]))
+        err = np.max(np.abs(grad[b] - ref["grad"])) / gmax
+        print(f"[fullsize] cfg2 {prec} member {b}: |dF| = {abs(F[b] - ref['F']):.2e}, grad err {err:.2e}",
+              flush=True)
+        assert err <= gtol, (b, err)

@@ -45,7 +45,7 @@ def test_random_problem_matches_oracle(gpu_lib, case):
     F, g = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec, chunk=chunk, hbm_budget=budget)
     gmax = max(np.max(np.abs(ref["grad"])), 1e-300)
     if prec == "fp64":
-        assert abs(F - ref["F"]) <= 1e-10 * max(ref["F"], 1e-3)
+        assert abs(F - ref["F"]) <= 1e-10 * ref["F"]
         assert np.max(np.abs(g - ref["grad"])) <= 1e-10 * gmax
     else:
         assert abs(F - ref["F"]) <= 1e-5

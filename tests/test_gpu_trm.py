@@ -1,0 +1,100 @@
+"""GPU parity of the trust-region method on the GRAPE residual.
+
+* qoc_trace_gradient_dev (d Tr(W^dag X_N)/du, complex) against the oracle's
+  sum_ab conj(W_ab) d(X_N)_ab/du for random non-unitary W, every padding
+  class, FP64 and FP32.
+* The Jacobian J built on the device (d^2 batched trace gradients plus the
+  phi column) against the oracle's, element by element, and J v and J^T r
+  against the oracle's products.
+* The device TRM against the oracle TRM on the same problem: same accepted
+  f values and parameters after several iterations (FP64).
+* Convergence on configuration 2 (4-qubit Heisenberg chain, d = 16, m = 8,
+  N = 1000): f decreases on every accepted step and F rises to the target.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import trm as T
+from workloads import make_config, make_random
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("d,prec", [(3, "fp64"), (16, "fp64"), (40, "fp32"), (100, "fp64"), (64, "fp32")])
+def test_trace_gradient_matches_oracle(gpu_lib, d, prec):
+    import torch
+    from paper_2208_12187_amd import qoc
+
+    m, N = 3, 9
+    p = make_random(400 + d, d, m, N, 0.05)
+    W = np.random.default_rng(d).standard_normal((d, d)) + 1j * np.random.default_rng(d + 1).standard_normal((d, d))
+    XN, dX = T.grape_xn_jacobian(p.H0, p.Hc, p.u, p.dt)
+    g_ref = np.sum(W.conj() * XN)
+    dg_ref = np.einsum("ab,jkab->jk", W.conj(), dX)
+    print(f"[trm] trace gradient d={d} {prec}", flush=True)
+    b = qoc.Batch.from_problems([p.with_target(W)])
+    r = qoc.Runner(1, d, m, N, prec)
+    g, dg = r.trace_gradient(b)
+    torch.cuda.synchronize()
+    g, dg = g.cpu().numpy()[0], dg.cpu().numpy()[0]
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert abs(g - g_ref) <= tol * max(1.0, abs(g_ref))
+    assert np.max(np.abs(dg - dg_ref)) <= tol * np.max(np.abs(dg_ref))
+
+
+def test_jacobian_and_its_products_match_oracle(gpu_lib):
+    import torch
+    from paper_2208_12187_amd import trm
+
+    p = make_random(21, 4, 3, 7, 0.1)
+    phi = 0.81
+    lsq = trm.GrapeLSQ(p, "fp64")
+    x = torch.tensor(np.concatenate([p.u.ravel(), [phi]]), device="cuda")
+    J = lsq.jacobian(x).cpu().numpy()
+    r = lsq.residual(x).cpu().numpy()
+    J_ref = T.grape_residual_jacobian(p.H0, p.Hc, p.u, p.dt, p.V, phi)
+    r_ref = T.grape_residual(p.H0, p.Hc, p.u, p.dt, p.V, phi)
+    assert J.shape == J_ref.shape == (2 * 16, 3 * 7 + 1)
+    assert np.max(np.abs(J - J_ref)) <= 1e-10 * np.max(np.abs(J_ref))
+    assert np.max(np.abs(r - r_ref)) <= 1e-12
+    v = np.random.default_rng(3).standard_normal(J.shape[1])
+    assert np.max(np.abs(J @ v - J_ref @ v)) <= 1e-10 * np.max(np.abs(J_ref @ v))
+    # J^T r through one trace gradient with the residual matrix as the target
+    R = torch.tensor((r_ref[:16] + 1j * r_ref[16:]).reshape(4, 4), device="cuda")
+    jtr = lsq.trace_gradient(x, R).real.cpu().numpy().ravel()
+    ref = (J_ref.T @ r_ref)[:-1]
+    assert np.max(np.abs(jtr - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_device_trm_follows_the_oracle(gpu_lib):
+    from paper_2208_12187_amd import trm
+
+    p = make_config(2, N=30)
+    # a tight sigma: with the default 0.1 the Levenberg-Marquardt iteration
+    # may stop one update earlier or later on either side of the band from
+    # rounding-level differences in J, which changes the step within the band
+    kw = dict(max_iter=6, gtol=1e-14, ftol=0.0, sigma=1e-9)
+    u_ref, phi_ref, info_ref = T.grape_trm(p, **kw)
+    u, phi, info = trm.trm_grape(p, "fp64", **kw)
+    print(f"[trm] oracle f {info_ref['f']}\n[trm] device f {info['f']}", flush=True)
+    assert len(info["f"]) == len(info_ref["f"])
+    assert np.max(np.abs(np.array(info["f"]) - info_ref["f"])) <= 1e-9 * info_ref["f"][0]
+    assert [s[3] for s in info["steps"]] == [s[3] for s in info_ref["steps"]]
+    assert np.max(np.abs(u - u_ref)) <= 1e-6 * max(1.0, np.max(np.abs(u_ref)))
+    assert abs(phi - phi_ref) <= 1e-6
+
+
+def test_trm_converges_on_config2(gpu_lib):
+    from paper_2208_12187_amd import trm
+
+    p = make_config(2)
+    u, phi, info = trm.trm_grape(p, "fp64", max_iter=25, log=lambda s: print(s, flush=True))
+    F0, F1 = info["F"][0], info["F"][-1]
+    print(f"[trm] configuration 2: F {F0:.3e} -> {F1:.8f} in {len(info['steps'])} iterations, "
+          f"{info['seconds']:.2f} s (Jacobians {info['jac_s']:.2f} s, SVD {info['svd_s']:.2f} s), {info['reason']}",
+          flush=True)
+    assert all(b < a for a, b in zip(info["f"], info["f"][1:]))
+    assert F1 > 0.99
+    ref = oracle.fidelity_ref(p.with_u(u))
+    assert abs(ref["F"] - F1) <= 1e-10
