@@ -83,7 +83,16 @@ def generators(H0, Hc, Ls):
 def lindblad_gradient(H0, Hc, Ls, u, dt, V):
     """Returns (F, g, grad (m x N), X_N) of the open-system problem."""
     G0, Gc = generators(H0, Hc, Ls)
-    T = target_superop(V)
+    return generator_gradient(G0, Gc, u, dt, target_superop(V))
+
+
+def generator_gradient(G0, Gc, u, dt, T):
+    """The same for any generators G0, Gc[j] (D x D) and target T (D x D):
+    S_k = exp(dt (G0 + sum_j u[j, k] Gc[j])), g = Tr(T^dag X_N), F = |g|^2 / D^2.
+    Returns (F, g, grad, X_N)."""
+    G0 = np.asarray(G0, dtype=np.complex128)
+    Gc = np.asarray(Gc, dtype=np.complex128)
+    T = np.asarray(T, dtype=np.complex128)
     u = np.asarray(u, dtype=np.float64)
     m, N = u.shape
     D = G0.shape[0]
