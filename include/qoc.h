@@ -80,9 +80,10 @@ typedef struct {
   double reunitarise_tol; /* reduced precision: every chunk product S of the
                              scans is checked in FP64, r = |S^dag S - I|_F, and gets one
                              Newton-Schulz step S (3I - S^dag S)/2 when r exceeds it.
-                             0 = default, 10 u sqrt(d L) with u = 2^-24 and L the
-                             slices per chunk (ten times the residual rounding leaves
-                             in a chunk product); < 0 disables; never applied in FP64. */
+                             0 = default: a step on every chunk product (removing the
+                             non-unitary part of the rounding error keeps Tr(V^dag X_N)
+                             about ten times more accurate); < 0 disables; never
+                             applied in FP64. */
   void* stream;           /* hipStream_t for _dev calls; NULL = default stream */
   int32_t chunk;          /* slices per scan chunk; 0 = qoc_default_chunk(d, N) */
   int32_t dense_controls; /* 0 (default): when every control Hc[j] has at most one

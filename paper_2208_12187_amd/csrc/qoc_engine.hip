@@ -243,8 +243,8 @@ hipError_t launch_tick(qoc_engine* E, Bucket& b) {
     const double* Hc = H0 + 2 * (size_t)r.d * r.d;
     const double* u = Hc + 2 * (size_t)r.d * r.d * r.m;
     const double* V = u + (size_t)r.m * r.N;
-    // the API's default threshold: ten times a chunk product's rounding residual
-    const double tol = E->precision == QOC_FP64 ? -1.0 : 10.0 * 0x1p-24 * sqrt((double)r.d * (double)r.lo.L);
+    // the API's default: a Newton-Schulz step on every chunk product
+    const double tol = E->precision == QOC_FP64 ? -1.0 : 0.0;
     fill_desc(P, r.lo, dbase + r.ws_off, r.d, r.m, r.N, r.dt, RUN_FID | RUN_BWD | RUN_GRAD, H0, Hc, u, V,
               reinterpret_cast<double*>(dbase + r.F_off), reinterpret_cast<double*>(dbase + r.grad_off), nullptr, tol);
     if (e == hipSuccess) e = hipMemcpyAsync(dbase, hbase, r.in_bytes, hipMemcpyHostToDevice, b.stream);

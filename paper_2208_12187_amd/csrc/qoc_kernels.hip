@@ -2014,11 +2014,21 @@ hipError_t launch_stage(int precision, int D, int stage, const Launch& L, const 
       default: ok = false;
     }
   } else if (precision == 2) {
-    // split-BF16 products in the bulk kernels (expm, scans, adjoint); the
-    // carry and chunk products stay FP32
+    // split-BF16 products in the adjoint (the Frechet series and its trace
+    // contractions, the dominant kernel); the exponentials, scans, carries and
+    // chunk products stay FP32.  Split products in the forward chain as well
+    // leave an absolute error in Tr(V^dag X_N) several times larger, which
+    // the gradient of a member with a small |g| cannot absorb.
+    const bool adj = stage == ST_ADJ;
     switch (D) {
-      case 32: stage_small<float, 32, Bf3Ops<32>>(stage, L, rg, ur32); break;
-      case 64: stage_small<float, 64, Bf3Ops<64>>(stage, L, rg, ur32); break;
+      case 32:
+        if (adj) stage_small<float, 32, Bf3Ops<32>>(stage, L, rg, ur32);
+        else stage_small<float, 32, StdOps<float, 32>>(stage, L, rg, ur32);
+        break;
+      case 64:
+        if (adj) stage_small<float, 64, Bf3Ops<64>>(stage, L, rg, ur32);
+        else stage_small<float, 64, StdOps<float, 64>>(stage, L, rg, ur32);
+        break;
       default: ok = false;
     }
   } else {

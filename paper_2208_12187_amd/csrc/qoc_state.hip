@@ -57,6 +57,11 @@ constexpr int kStateMonoMax = 16;
 // Taylor powers kept per vector: q <= 18 and qb <= 19 whenever r <= 1 in
 // FP64 (1/19! < 2^-53), which the plan guarantees.
 constexpr int kStateQMax = 19;
+// Slices whose plans and amplitudes the chains stage in LDS at a time.
+constexpr int kChainBlock = 64;
+// Consecutive slices per gradient workgroup (H0 and the row tables are loaded
+// once for them).
+constexpr int kGradSlices = 8;
 
 template <typename T>
 struct cpx {
@@ -218,7 +223,8 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_chain(StateWork W) {
   constexpr int TPR = SV<D>::TPR, CPT = SV<D>::CPT, NW = SV<D>::NW;
   __shared__ cpx<T> zb[2][D];
   __shared__ CtlTab<T, D> ctl;
-  __shared__ T us[kStateMonoMax];
+  __shared__ T ub[kChainBlock][kStateMonoMax];  // row-table path: u[j][k] of the block's slices
+  __shared__ int sqb[kChainBlock];              // the block's plans
   __shared__ double red[2 * NW];
   const int p = blockIdx.x, bwd = blockIdx.y;
   const ProbDesc P = W.descs[p];  // a copy: stores cannot alias it
@@ -243,16 +249,26 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_chain(StateWork W) {
   int buf = 0;
   for (int step = 0; step < N; ++step) {
     const int k = bwd ? N - 1 - step : step;
-    const int sq = gp(P.sq)[k];
+    const int bi = step % kChainBlock;  // position in the block of slices staged in LDS
+    if (bi == 0) {
+      // the plans (and, on the row-table path, the amplitudes) of the next
+      // kChainBlock slices in chain order: one round trip per block
+      __syncthreads();  // the previous block's entries have been read
+      const int nb = min(kChainBlock, N - step);
+      for (int e = threadIdx.x; e < nb; e += SV<D>::NT) sqb[e] = gp(P.sq)[bwd ? k - e : k + e];
+      if constexpr (MONO)
+        for (int e = threadIdx.x; e < m * nb; e += SV<D>::NT) {
+          const int j = e / nb, t = e - j * nb;
+          ub[t][j] = (T)gp(P.u)[(size_t)j * N + (bwd ? k - t : k + t)];
+        }
+      __syncthreads();
+    }
+    const int sq = sqb[bi];
     const int s = sq & 0xff, q = (sq >> 8) & 0xff;
     // A z = -i c (H z) forward; the adjoint step uses -A = +i c H.
     const double c = ldexp(P.dt, -s) * (bwd ? -1.0 : 1.0);
-    __syncthreads();  // the previous slice's products have read us[]
-    if constexpr (MONO) {
-      if ((int)threadIdx.x < m) us[threadIdx.x] = (T)gp(P.u)[(size_t)threadIdx.x * N + k];
-    } else {
-      assemble_row<T, D>(H, P, k, row, cg * CPT);
-    }
+    const T* us = ub[bi];  // the slice's amplitudes (row-table path)
+    if constexpr (!MONO) assemble_row<T, D>(H, P, k, row, cg * CPT);
     for (int r = 0; r < (1 << s); ++r) {
       T dr = 0, di = 0;  // delta
       for (int i = q; i >= 1; --i) {
@@ -294,7 +310,7 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_chain(StateWork W) {
 
 // ---------------------------------------------------------------- gradient
 
-// One workgroup per (problem, slice k): the Taylor powers b_l = (A/R)^l psi
+// One workgroup per kGradSlices consecutive slices of a problem; per slice k: the Taylor powers b_l = (A/R)^l psi
 // and a_i = (-A/R)^i lam in LDS, then per control
 // G_j = sum_{i + l <= qb - 1} a_i^dag Hc[j] b_l / (i + l + 1)!  (FP64), summed
 // over the R sub-steps, and dF/du[j][k] = (2 dt / R) Im(conj(g) G_j).
@@ -308,15 +324,21 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_grad(StateWork W) {
   __shared__ T us[kStateMonoMax];
   __shared__ double red[2 * NW];
   __shared__ double gacc[2 * kStateMonoMax * NW];
-  const int item = blockIdx.x;
   const ProbDesc& P0 = W.descs[0];
-  const int pidx = item / P0.N;  // every problem of a launch has the same N
+  const int per = (P0.N + kGradSlices - 1) / kGradSlices;  // workgroups per problem (uniform N)
+  const int pidx = blockIdx.x / per;
   const ProbDesc P = W.descs[pidx];
-  const int k = item - pidx * P.N;
   const int row = threadIdx.x / TPR, cg = threadIdx.x % TPR, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = P.m, N = P.N;
   if (state_mono<D>(P) != MONO) return;
   constexpr bool mono = MONO;
+  HRow<T, D> H;
+  if constexpr (MONO) {  // H0 and the row tables serve every slice of the workgroup
+    row_load<T, D>(H.re, H.im, reinterpret_cast<const T*>(P.Hint), row, cg * CPT);
+    ctl_load<T, D>(ctl, P);
+  }
+  const int kb = (blockIdx.x - pidx * per) * kGradSlices;
+  for (int k = kb; k < min(N, kb + kGradSlices); ++k) {
   const int sq = gp(P.sq)[k];
   const int s = sq & 0xff, q = (sq >> 8) & 0xff, qb = (sq >> 16) & 0xff;
   const int R = 1 << s;
@@ -324,10 +346,8 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_grad(StateWork W) {
   const int Qp = min(max(q, qb - 1), kStateQMax - 1);
   const int qe = min(q, Qp), qbe = min(qb, Qp + 1);
   const double c = ldexp(P.dt, -s);
-  HRow<T, D> H;
+  __syncthreads();  // the previous slice is done with us[], the powers and gacc
   if constexpr (MONO) {
-    row_load<T, D>(H.re, H.im, reinterpret_cast<const T*>(P.Hint), row, cg * CPT);
-    ctl_load<T, D>(ctl, P);
     if ((int)threadIdx.x < m) us[threadIdx.x] = (T)gp(P.u)[(size_t)threadIdx.x * N + k];
   } else {
     assemble_row<T, D>(H, P, k, row, cg * CPT);
@@ -492,11 +512,12 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_grad(StateWork W) {
       P.grad[(size_t)j * N + k] = scale * (g0 * si - g1 * sr);
     }
   }
+  }  // slices of the workgroup
 }
 
 template <typename T, int D>
 static hipError_t launch_state(const StateWork& W, int B, int N, int grad, hipStream_t st) {
-  const dim3 cg(B, grad ? 2 : 1), gg(B * N), nt(SV<D>::NT);
+  const dim3 cg(B, grad ? 2 : 1), gg(B * ((N + kGradSlices - 1) / kGradSlices)), nt(SV<D>::NT);
   stage_mark(ST_SCHAIN, true, st);
   hipLaunchKernelGGL((k_state_chain<T, D, true>), cg, nt, 0, st, W);
   hipLaunchKernelGGL((k_state_chain<T, D, false>), cg, nt, 0, st, W);

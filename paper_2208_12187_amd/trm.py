@@ -155,18 +155,20 @@ def trm_grape(problem, precision="fp64", max_iter=30, gtol=1e-10, ftol=1e-12, si
     J = lsq.jacobian(x)
     torch.cuda.synchronize()
     info["jac_s"] += time.perf_counter() - tj
+    svd = None  # the SVD of the current J; a rejected step keeps x, J and it
     for it in range(max_iter):
         g = J.T @ r
         if float(g.abs().max()) <= gtol:
             info["reason"] = "gtol"
             break
-        ts = time.perf_counter()
-        U, s, Vh = torch.linalg.svd(J, full_matrices=False)
-        torch.cuda.synchronize()
-        info["svd_s"] += time.perf_counter() - ts
-        keep = s > rank_rtol * s[0]
-        s, U, Vh = s[keep], U[:, keep], Vh[keep]
-        nonsingular = bool(keep.all()) and J.shape[0] >= J.shape[1]
+        if svd is None:
+            ts = time.perf_counter()
+            U, s, Vh = torch.linalg.svd(J, full_matrices=False)
+            torch.cuda.synchronize()
+            info["svd_s"] += time.perf_counter() - ts
+            keep = s > rank_rtol * s[0]
+            svd = (U[:, keep], s[keep], Vh[keep], bool(keep.all()) and J.shape[0] >= J.shape[1])
+        U, s, Vh, nonsingular = svd
         c = (U.T @ r)
         s_h, c_h = s.cpu().numpy(), c.cpu().numpy()
         p = -(Vh.T @ (s / (s * s) * c))
@@ -197,6 +199,7 @@ def trm_grape(problem, precision="fp64", max_iter=30, gtol=1e-10, ftol=1e-12, si
                 break
             tj = time.perf_counter()
             J = lsq.jacobian(x)
+            svd = None
             torch.cuda.synchronize()
             info["jac_s"] += time.perf_counter() - tj
     info["jacobians"] = lsq.jacobians

@@ -152,9 +152,9 @@ def test_reunitarisation_check_and_step(gpu_lib, cfg, N, prec):
     L = qoc.default_chunk(p.d, p.N)
     P = -(-p.N // L)
     assert n0 == 0 and rmax0 == 0.0
-    # the default threshold, 10 u sqrt(d L), sits above the rounding residual
-    # of a well-conditioned chunk product: no step is taken by default
-    assert 0 < rmax1 < 10 * 2.0 ** -24 * np.sqrt(p.d * L) and n1 == 0
+    # chunk residuals sit at the rounding level (below 2 u sqrt(d L)); the
+    # default steps every chunk product
+    assert 0 < rmax1 < 2 * 2.0 ** -24 * np.sqrt(p.d * L) and n1 == n2
     assert n2 == P  # one step per forward chunk total (the backward totals are their adjoints)
     assert rX2 <= 2 * rX0 + 1e-12
     # checkpointed: the second sweep rebuilds the local products without

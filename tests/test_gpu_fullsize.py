@@ -16,10 +16,12 @@ Configuration 4 (7-qubit Heisenberg chain, d = 128, m = 14, N = 1000) is
 checked the same way at its benchmark batch of 8, with one member against
 the oracle.
 
-The split-BF16 path keeps about 16 bits per product.  At this size its F
-meets the gate, but its gradient does not for every member: on member 31,
-whose gradient is small (max|grad| = 2.5e-8), the error is 3.6e-4 of
-max|grad|, above the 1e-4 gate.  That gate is checked in a strict xfail."""
+The gradient gate (1e-4 of max|grad|) is met by every precision on the
+sampled members, member 31 among them: its gradient is small (max|grad| =
+2.5e-8), so an absolute error in Tr(V^dag X_N) shows there first.  The
+default Newton-Schulz step on every chunk product and FP32 forward chains
+for the split-BF16 precision keep that error down (measured 7.5e-6 FP32 and
+1.6e-5 split BF16 of max|grad| over all 32 members)."""
 import numpy as np
 import pytest
 
@@ -94,8 +96,7 @@ def test_config3_batch_of_32(gpu_lib, problems, refs, prec):
     for i in SAMPLED:
         ref = refs[i]
         assert abs(Fh[i] - ref["F"]) <= (ftol * ref["F"] if rel else ftol), (i, Fh[i], ref["F"])
-    if prec != "bf16x3":
-        _grad_gate(gh, refs, prec)
+    _grad_gate(gh, refs, prec)
 
     _properties(problems, Fh, gh)
 
@@ -104,13 +105,6 @@ def test_config3_batch_of_32(gpu_lib, problems, refs, prec):
     Fa, ga = alone.gradient(qoc.Batch.from_problems([problems[i]]))
     torch.cuda.synchronize()
     assert Fa[0].item() == Fh[i] and np.array_equal(ga[0].cpu().numpy(), gh[i])
-
-
-@pytest.mark.xfail(strict=True, reason="split BF16 carries about 16 bits per product; at N = 2000 its gradient "
-                   "error on a member with a small gradient exceeds 1e-4 of max|grad|")
-def test_bf16x3_gradient_gate_at_full_size(gpu_lib, problems, refs):
-    _, gh = _run_batch(problems, "bf16x3")
-    _grad_gate(gh, refs, "bf16x3")
 
 
 B4, SAMPLED4 = 8, 5
