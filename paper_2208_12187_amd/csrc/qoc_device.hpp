@@ -512,6 +512,31 @@ __device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
   return t;
 }
 
+// The same over the G consecutive lanes of each aligned lane group
+// (V <= G <= 64, both powers of two): afterwards lane l holds its group's
+// total of value (l % G) / (G / V).
+template <int V, int G>
+__device__ __forceinline__ double group_sum_many(double (&v)[V], int lane) {
+  static_assert(V >= 1 && V <= G && G <= 64 && (V & (V - 1)) == 0 && (G & (G - 1)) == 0, "powers of two");
+  constexpr int LOG = __builtin_ctz(V);
+#pragma unroll
+  for (int s = 0; s < LOG; ++s) {
+    const int o = (G / 2) >> s;
+    const int H = V >> (s + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = up ? v[i + H] : v[i];
+      const double give = up ? v[i] : v[i + H];
+      v[i] = keep + __shfl_xor(give, o, 64);
+    }
+  }
+  double t = v[0];
+#pragma unroll
+  for (int o = (G / 2) >> LOG; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
 }  // namespace qoc
 
 namespace qoc {

@@ -501,6 +501,19 @@ __device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel
 // doubles of LDS (double-buffered by group).
 constexpr int kEpiGroup = 4;
 
+// Stores the gradient entry (j, k) from T_j = a + i b.
+__device__ __forceinline__ void grad_put(const ProbDesc& P, int j, int k, double a, double b) {
+  if (P.flags & RUN_RAWDG) {
+    // dg/du[j][k] = -i dt Tr(Z_k^dag Hc[j]), complex interleaved
+    const size_t o = 2 * ((size_t)j * P.N + k);
+    gp(P.grad)[o] = P.dt * b;
+    gp(P.grad)[o + 1] = -P.dt * a;
+  } else {
+    const double pref = 2.0 * P.dt / ((double)P.d * P.d);
+    gp(P.grad)[(size_t)j * P.N + k] = pref * (gp(P.g)[0] * b - gp(P.g)[1] * a);
+  }
+}
+
 template <int NWAVES>
 __device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j0, int grp, double (&v)[2 * kEpiGroup],
                                                  const Lane& L, double* red) {
@@ -518,15 +531,7 @@ __device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j
       a += rg[(2 * jj) * NWAVES + w];
       b += rg[(2 * jj + 1) * NWAVES + w];
     }
-    if (P.flags & RUN_RAWDG) {
-      // dg/du[j][k] = -i dt Tr(Z_k^dag Hc[j]), complex interleaved
-      const size_t o = 2 * ((size_t)(j0 + jj) * P.N + k);
-      gp(P.grad)[o] = P.dt * b;
-      gp(P.grad)[o + 1] = -P.dt * a;
-    } else {
-      const double pref = 2.0 * P.dt / ((double)P.d * P.d);
-      gp(P.grad)[(size_t)(j0 + jj) * P.N + k] = pref * (gp(P.g)[0] * b - gp(P.g)[1] * a);
-    }
+    grad_put(P, j0 + jj, k, a, b);
   }
 }
 
@@ -551,25 +556,39 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
   panel_to_lds(zl, Z, L);
   __syncthreads();
   if (mono) {
+    // The D threads of lane group jj = t / D (aligned inside one wavefront)
+    // take row a = t % D of controls jj, jj + 4, jj + 8, jj + 12 of each
+    // pass of 16, so that one control's sum stays inside one lane group: one
+    // multi-value group reduction per pass and no barrier.
+    constexpr int CPT = 4;
+    constexpr int V = 2 * CPT;
+    constexpr int GV = D / V;  // lanes per reduced value
     const int a = threadIdx.x % D, jj = threadIdx.x / D;
     const T* mv = reinterpret_cast<const T*>(P.mval);
-    for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
-      double v[2 * kEpiGroup];
-      double tr = 0, ti = 0;
-      if (j0 + jj < P.m) {
-        const size_t idx = (size_t)(j0 + jj) * D + a;
-        const int off = lds_off<T, D>(a, gp(P.mcol)[idx]);
-        const double zr = (double)zl[off], zi = (double)zl[D * SD + off];
-        const double x = (double)gp(mv)[2 * idx], y = (double)gp(mv)[2 * idx + 1];
-        tr = zr * x + zi * y;  // conj(z) h
-        ti = zr * y - zi * x;
-      }
+    for (int j0 = 0; j0 < P.m; j0 += kEpiGroup * CPT) {
+      double v[V];
 #pragma unroll
-      for (int q = 0; q < kEpiGroup; ++q) {
-        v[2 * q] = q == jj ? tr : 0.0;
-        v[2 * q + 1] = q == jj ? ti : 0.0;
+      for (int i = 0; i < CPT; ++i) {
+        const int j = j0 + jj + kEpiGroup * i;
+        double tr = 0, ti = 0;
+        if (j < P.m) {
+          const size_t idx = (size_t)j * D + a;
+          const int off = lds_off<T, D>(a, gp(P.mcol)[idx]);
+          const double zr = (double)zl[off], zi = (double)zl[D * SD + off];
+          const double x = (double)gp(mv)[2 * idx], y = (double)gp(mv)[2 * idx + 1];
+          tr = zr * x + zi * y;  // conj(z) h
+          ti = zr * y - zi * x;
+        }
+        v[2 * i] = tr;
+        v[2 * i + 1] = ti;
       }
-      epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
+      const double t = group_sum_many<V, D>(v, L.lane);
+      const double t1 = __shfl_xor(t, GV, 64);  // the other half of the complex sum
+      const int vi = a / GV;
+      if (a % GV == 0 && (vi & 1) == 0) {
+        const int j = j0 + jj + kEpiGroup * (vi >> 1);
+        if (j < P.m) grad_put(P, j, k, t, t1);
+      }
     }
     return;
   }
