@@ -20,10 +20,13 @@ from . import qoc
 
 
 def replay(problems, arrivals, precision="fp32", max_active=256, pool_bytes=96 << 30, host_bytes=8 << 30,
-           keep_grad=False, engine=None, progress=None):
+           keep_grad=False, engine=None, progress=None, idle_sleep=1e-4):
     """Submit problems[i] at arrivals[i] seconds after the start (all at once if
     every arrival is 0) and collect results.  Returns a dict with per-request
-    latency, F (and gradients when keep_grad), makespan and throughput."""
+    latency, F (and gradients when keep_grad), makespan and throughput.
+    While nothing has finished and the next arrival is ahead, the loop sleeps
+    at most idle_sleep seconds before polling again (0: spin), which bounds
+    how late a finished request is noticed."""
     n = len(problems)
     own = engine is None
     eng = engine or qoc.Engine(precision, pool_bytes, host_bytes, max_active)
@@ -58,8 +61,8 @@ def replay(problems, arrivals, precision="fp32", max_active=256, pool_bytes=96 <
                     print(f"[serve] {done}/{n} done at {t:.2f} s", flush=True)
             if not got and nxt < n:
                 gap = arrivals[order[nxt]] - (time.perf_counter() - t0)
-                if gap > 2e-4:
-                    time.sleep(min(gap, 1e-3))
+                if idle_sleep > 0 and gap > 2 * idle_sleep:
+                    time.sleep(min(gap, idle_sleep))
         makespan = time.perf_counter() - t0
     finally:
         if own:
@@ -111,6 +114,35 @@ def poisson_arrivals(n, rate, seed=5):
     return np.cumsum(gaps) - gaps[0]
 
 
+def run(n_requests=4096, precision="fp32", load=0.7, max_active=256, seed=5, log=None):
+    """The serving benchmark: the trace offered all at once (capacity), then
+    replayed with Poisson arrivals at `load` times that capacity, batched and
+    again one request at a time on the same arrival times.  Returns the
+    summary dict."""
+    say = log or (lambda msg: None)
+    t0 = time.perf_counter()
+    trace, problems = build_requests(n_requests, seed)
+    n = len(problems)
+    say(f"[serve] built {n} requests in {time.perf_counter() - t0:.1f} s")
+    prog = max(1, n // 8)
+    cap = replay(problems, np.zeros(n), precision, max_active, progress=prog if log else None)
+    capacity = cap["requests_per_s"]
+    rate = load * capacity
+    say(f"[serve] capacity {capacity:.1f} req/s; replaying at {rate:.1f} req/s")
+    arr = poisson_arrivals(n, rate, seed)
+    mix = replay(problems, arr, precision, max_active, progress=prog if log else None)
+    say(f"[serve] batched: {summary(mix)}")
+    alone = replay(problems, arr, precision, 1, progress=prog if log else None)
+    say(f"[serve] one at a time: {summary(alone)}")
+    return {"requests": n, "precision": precision, "trace_seed": seed,
+            "capacity_req_per_s": round(capacity, 1),
+            "capacity_slice_steps_per_s": round(cap["slice_steps_per_s"], 1),
+            "arrival_rate_req_per_s": round(rate, 1), "load": load,
+            "batched": summary(mix), "one_at_a_time": summary(alone),
+            "max_abs_dF_batched_vs_alone": float(np.max(np.abs(mix["F"] - alone["F"]))),
+            "per_d": {"batched": per_d(mix, problems), "one_at_a_time": per_d(alone, problems)}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="GRAPE serving benchmark")
     ap.add_argument("--requests", type=int, default=4096)
@@ -119,25 +151,9 @@ def main(argv=None):
     ap.add_argument("--max-active", type=int, default=256)
     ap.add_argument("--seed", type=int, default=5)
     args = ap.parse_args(argv)
-    t0 = time.perf_counter()
-    trace, problems = build_requests(args.requests, args.seed)
-    n = len(problems)
-    print(f"[serve] built {n} requests in {time.perf_counter() - t0:.1f} s", flush=True)
-    zero = np.zeros(n)
-    prog = max(1, n // 8)
-    cap = replay(problems, zero, args.precision, args.max_active, progress=prog)
-    capacity = cap["requests_per_s"]
-    rate = args.load * capacity
-    print(f"[serve] capacity {capacity:.1f} req/s; replaying at {rate:.1f} req/s", flush=True)
-    arr = poisson_arrivals(n, rate, args.seed)
-    mix = replay(problems, arr, args.precision, args.max_active, progress=prog)
-    print(f"[serve] batched: {summary(mix)}", flush=True)
-    alone = replay(problems, arr, args.precision, 1, progress=prog)
-    out = {"requests": n, "precision": args.precision, "capacity_req_per_s": round(capacity, 1),
-           "capacity_slice_steps_per_s": round(cap["slice_steps_per_s"], 1),
-           "arrival_rate_req_per_s": round(rate, 1), "batched": summary(mix), "one_at_a_time": summary(alone),
-           "max_abs_dF_batched_vs_alone": float(np.max(np.abs(mix["F"] - alone["F"]))),
-           "per_d": {"batched": per_d(mix, problems), "one_at_a_time": per_d(alone, problems)}}
+    # progress on stderr, the summary as the one line on stdout
+    out = run(args.requests, args.precision, args.load, args.max_active, args.seed,
+              log=lambda msg: print(msg, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 
