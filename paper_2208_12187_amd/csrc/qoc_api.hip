@@ -108,7 +108,8 @@ qoc_options defaults() {
 // per-slice arrays hold one segment at a time: a first sweep over segments
 // (expm, forward scans) yields every chunk total, the carry and mc run once,
 // and a second sweep recomputes each segment's propagators and local products
-// before its adjoint pass.  The recomputation is bitwise identical.
+// (forward and backward passes in one launch) before its adjoint pass.  The
+// recomputation is bitwise identical.
 hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int flags) {
   using namespace qoc;
   const int D = Lo.D;
@@ -149,8 +150,7 @@ hipError_t enqueue(int precision, const Layout& Lo, const Launch& L, int N, int 
       Range rg = segment(c);
       rg.recompute = 1;
       run(ST_EXPM, rg);
-      run(ST_SCAN, rg);
-      run(ST_BSCAN, rg);
+      run(ST_SCAN, rg);  // the forward and backward passes of the segment together
       run(ST_ADJ, rg);
     }
   }

@@ -788,8 +788,9 @@ __device__ __forceinline__ void reunitarise(const ProbDesc& P, Panel<float, D>& 
 // Delta^dag S) with Delta staged in LDS, double-buffered.
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
-void k_scan_local(Work W, int bwd) {
+void k_scan_local(Work W, int dir) {
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
+  const int bwd = dir < 0 ? (int)blockIdx.y : dir;  // dir < 0: both passes, one per blockIdx.y
   __shared__ double red[D / 16];
   Lane L;
   const Items I(W);
@@ -1663,9 +1664,10 @@ __device__ __noinline__ void reunitarise128(const ProbDesc& P, float* Ypf, float
 }
 
 template <typename T>
-__global__ __launch_bounds__(512) void k_scan128(Work W, int bwd) {
+__global__ __launch_bounds__(512) void k_scan128(Work W, int dir) {
   __shared__ T lds[K128<T>::LDS_ELEMS];
   __shared__ double red[8];
+  const int bwd = dir < 0 ? (int)blockIdx.y : dir;  // dir < 0: both passes, one per blockIdx.y
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -1929,9 +1931,13 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
     case ST_SCAN:
     case ST_BSCAN: {
       Work w = L.dyn ? dyn : chunk_work(L, rg);
-      const int bwd = stage == ST_BSCAN ? 1 : 0;
-      if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w, bwd);
-      else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w, bwd);
+      // a recompute sweep runs the forward and backward passes of a segment
+      // together (they are independent once mc is known)
+      const bool both = stage == ST_SCAN && rg.recompute && !L.dyn;
+      const int dir = stage == ST_BSCAN ? 1 : (both ? -1 : 0);
+      const dim3 grid(grid_of(L, w.total, 0), both ? 2 : 1);
+      if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), grid, dim3(NT), 0, st, w, dir);
+      else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), grid, dim3(NT), 0, st, w, dir);
       break;
     }
     case ST_CARRY: {
@@ -1985,7 +1991,9 @@ static void stage_128(int stage, const Launch& L, const Range& rg, double ur) {
     case ST_SCAN:
     case ST_BSCAN: {
       Work w = L.dyn ? dyn : chunk_work(L, rg);
-      hipLaunchKernelGGL(k_scan128<T>, dim3(grid_of(L, w.total, 0)), dim3(512), 0, st, w, stage == ST_BSCAN ? 1 : 0);
+      const bool both = stage == ST_SCAN && rg.recompute && !L.dyn;
+      const int dir = stage == ST_BSCAN ? 1 : (both ? -1 : 0);
+      hipLaunchKernelGGL(k_scan128<T>, dim3(grid_of(L, w.total, 0), both ? 2 : 1), dim3(512), 0, st, w, dir);
       break;
     }
     case ST_CARRY: {
