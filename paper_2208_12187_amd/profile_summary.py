@@ -5,12 +5,18 @@
         <write counter_collection.csv> <copy GiB> [<counters json to write>]
 
     python -m paper_2208_12187_amd.profile_summary mfma <counter_collection.csv>
+    python -m paper_2208_12187_amd.profile_summary sq <counter_collection.csv>
 
 ``trace`` prints the per-kernel table of a ``--kernel-trace --stats`` run.
 ``mfma`` reads a run with the derived counters MfmaUtil (MFMA-busy cycles
 over GPU-active cycles times the SIMD count, in percent) and MfmaFlopsF32 /
 MfmaFlopsF64 / MfmaFlopsBF16 (512 times the MFMA operation counts) and prints
 their per-dispatch means for every kernel.
+``sq`` reads a run with wave-state counters (SQ_WAVE_CYCLES, SQ_WAIT_ANY,
+SQ_WAIT_INST_ANY, SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS,
+SQ_ACTIVE_INST_VMEM, SQ_WAIT_INST_LDS, SQ_LDS_BANK_CONFLICT) and prints, per
+kernel, each as a share of the wave-cycles (bank conflicts as a share of
+the LDS-active cycles).
 ``bytes`` reads one FETCH_SIZE pass and one WRITE_SIZE pass of the same
 command, calibrates each counter against the plain device-to-device copy of
 ``copy GiB`` that the bench makes before timing (``--copy-gib``; the copy
@@ -106,12 +112,37 @@ def mfma_table(path: str) -> str:
     return "\n".join(out)
 
 
+SQ_SHARES = ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+             "SQ_ACTIVE_INST_VMEM", "SQ_WAIT_INST_LDS")
+
+
+def sq_table(path: str) -> str:
+    vals = {n: per_kernel(path, n) for n in ("SQ_WAVE_CYCLES", "SQ_LDS_BANK_CONFLICT") + SQ_SHARES}
+    mean = lambda n, k: sum(vals[n].get(k, [0.0])) / max(len(vals[n].get(k, [])), 1)
+    head = " | ".join(n.replace("SQ_", "") for n in SQ_SHARES)
+    out = [f"| kernel | dispatches | {head} (share of wave-cycles) | LDS bank-conflict share of LDS-active |",
+           "|---|---|" + "---|" * (len(SQ_SHARES) + 1)]
+    for k in vals["SQ_WAVE_CYCLES"]:
+        if not k.startswith("qoc::"):
+            continue
+        wc = mean("SQ_WAVE_CYCLES", k)
+        if wc <= 0:
+            continue
+        shares = " | ".join(f"{mean(n, k) / wc:.3f}" for n in SQ_SHARES)
+        lds = mean("SQ_ACTIVE_INST_LDS", k)
+        bc = mean("SQ_LDS_BANK_CONFLICT", k) / lds if lds > 0 else 0.0
+        out.append(f"| `{k}` | {len(vals['SQ_WAVE_CYCLES'][k])} | {shares} | {bc:.3f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     a = sys.argv[1:] if argv is None else argv
     if a and a[0] == "trace" and len(a) == 2:
         print(trace_table(a[1]))
     elif a and a[0] == "mfma" and len(a) == 2:
         print(mfma_table(a[1]))
+    elif a and a[0] == "sq" and len(a) == 2:
+        print(sq_table(a[1]))
     elif a and a[0] == "bytes" and len(a) in (4, 5):
         print(bytes_table(a[1], a[2], float(a[3]), a[4] if len(a) == 5 else None))
     else:
