@@ -149,6 +149,88 @@ __device__ __forceinline__ void ctl_load(CtlTab<T, D>& C, const ProbDesc& P) {
   }
 }
 
+// The row-table control terms of this thread's row, held in registers for a
+// whole chain (the gradient kernel, whose register budget sets its
+// occupancy, reads them from the LDS table instead): controls j = cg, cg + TPR, ... (at most KC), their
+// columns col_j(row) and entries Hc[j][row][col_j], and the weighted entries
+// u[j][k] Hc[j][row][col_j] of the current slice.  Absent controls get
+// column `row` (in bounds) and weight 0.
+template <typename T, int D>
+struct CtlRegs {
+  static constexpr int KC = (kStateMonoMax + SV<D>::TPR - 1) / SV<D>::TPR;
+  int col[KC];
+  T vr[KC], vi[KC];
+  T wr[KC], wi[KC];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void ctl_regs_load(CtlRegs<T, D>& R, const CtlTab<T, D>& C, int m, int row, int cg) {
+#pragma unroll
+  for (int t = 0; t < CtlRegs<T, D>::KC; ++t) {
+    const int j = cg + SV<D>::TPR * t;
+    const int e = j * D + row;
+    R.col[t] = j < m ? C.col[e] : row;
+    R.vr[t] = j < m ? C.val[e].re : (T)0;
+    R.vi[t] = j < m ? C.val[e].im : (T)0;
+    R.wr[t] = R.wi[t] = 0;
+  }
+}
+
+// The slice's weights from its amplitudes us[j] (LDS).
+template <typename T, int D>
+__device__ __forceinline__ void ctl_regs_weigh(CtlRegs<T, D>& R, const T* us, int m, int cg) {
+#pragma unroll
+  for (int t = 0; t < CtlRegs<T, D>::KC; ++t) {
+    const int j = cg + SV<D>::TPR * t;
+    const T u = j < m ? us[j] : (T)0;
+    R.wr[t] = u * R.vr[t];
+    R.wi[t] = u * R.vi[t];
+  }
+}
+
+// y = (H z)[row] for this thread's row, complete in every lane of the row
+// group: H0 (or H_k) entries from registers, plus, on the row-table path
+// (R not null), sum over this thread's controls of w_j z[col_j].  The
+// control entries' vector reads are issued with the first group of columns.
+template <typename T, int D>
+__device__ __forceinline__ void row_apply_r(const HRow<T, D>& H, const cpx<T>* z, const CtlRegs<T, D>* R,
+                                            int cg, T& yr, T& yi) {
+  constexpr int CPT = SV<D>::CPT, TPR = SV<D>::TPR, KC = CtlRegs<T, D>::KC;
+  const int c0 = cg * CPT;
+  T ar = 0, ai = 0;
+  if (R) {
+    cpx<T> v[KC];
+#pragma unroll
+    for (int t = 0; t < KC; ++t) v[t] = z[R->col[t]];
+#pragma unroll
+    for (int t = 0; t < KC; ++t) {
+      ar = fma(R->wr[t], v[t].re, ar);
+      ar = fma(-R->wi[t], v[t].im, ar);
+      ai = fma(R->wr[t], v[t].im, ai);
+      ai = fma(R->wi[t], v[t].re, ai);
+    }
+  }
+#pragma unroll
+  for (int c4 = 0; c4 < CPT; c4 += 4) {
+#pragma unroll
+    for (int c = c4; c < c4 + 4; ++c) {
+      const cpx<T> v = z[c0 + c];
+      ar = fma(H.re[c], v.re, ar);
+      ar = fma(-H.im[c], v.im, ar);
+      ai = fma(H.re[c], v.im, ai);
+      ai = fma(H.im[c], v.re, ai);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int o = 1; o < TPR; o <<= 1) {
+    ar += __shfl_xor(ar, o, 64);
+    ai += __shfl_xor(ai, o, 64);
+  }
+  yr = ar;
+  yi = ai;
+}
+
 // y = (H z)[row] for this thread's row, complete in every lane of the row
 // group: H0 (or H_k) entries from registers, plus, on the row-table path,
 // sum over the controls j = cg, cg + TPR, ... of us[j] Hc[j][row][col_j] z[col_j].
@@ -233,9 +315,12 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_chain(StateWork W) {
   if (state_mono<D>(P) != MONO) return;
   constexpr bool mono = MONO;
   HRow<T, D> H;
+  CtlRegs<T, D> CR;
   if constexpr (MONO) {
     row_load<T, D>(H.re, H.im, reinterpret_cast<const T*>(P.Hint), row, cg * CPT);
     ctl_load<T, D>(ctl, P);
+    __syncthreads();
+    ctl_regs_load<T, D>(CR, ctl, m, row, cg);
   }
   // the chain's vector: x[row], held by every lane of the row group
   const double* src = bwd ? P.chiz : P.psi0z;
@@ -267,15 +352,15 @@ __global__ __launch_bounds__(SV<D>::NT) void k_state_chain(StateWork W) {
     const int s = sq & 0xff, q = (sq >> 8) & 0xff;
     // A z = -i c (H z) forward; the adjoint step uses -A = +i c H.
     const double c = ldexp(P.dt, -s) * (bwd ? -1.0 : 1.0);
-    const T* us = ub[bi];  // the slice's amplitudes (row-table path)
-    if constexpr (!MONO) assemble_row<T, D>(H, P, k, row, cg * CPT);
+    if constexpr (MONO) ctl_regs_weigh<T, D>(CR, ub[bi], m, cg);  // the slice's amplitudes
+    else assemble_row<T, D>(H, P, k, row, cg * CPT);
     for (int r = 0; r < (1 << s); ++r) {
       T dr = 0, di = 0;  // delta
       for (int i = q; i >= 1; --i) {
         if (cg == 0) zb[buf][row] = cpx<T>{xr + dr, xi + di};
         __syncthreads();
         T yr, yi;
-        row_apply<T, D>(H, zb[buf], mono ? &ctl : nullptr, us, m, row, cg, yr, yi);
+        row_apply_r<T, D>(H, zb[buf], mono ? &CR : nullptr, cg, yr, yi);
         const T f = (T)(c / i);
         dr = f * yi;  // -i f (yr + i yi) = f yi - i f yr
         di = -f * yr;
