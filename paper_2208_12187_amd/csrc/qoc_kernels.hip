@@ -19,6 +19,8 @@
 // the propagator.  Everything runs in "delta form": the Taylor sum keeps
 // T(X) - I and a squaring maps D to 2D + D^2, so that rounding errors scale
 // with |A| rather than with |U| = 1.
+#include <type_traits>
+
 #include "qoc_device.hpp"
 #include "qoc_internal.hpp"
 #include "qoc_plan.hpp"
@@ -233,6 +235,11 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
 
 // ---------------------------------------------------------------- assembly
 
+// The planar LDS layout of panel_to_lds (StdOps), which assemble's scatter
+// form writes and reads directly.
+template <typename T, int D, typename Ops>
+constexpr bool kStdLds = std::is_same<Ops, StdOps<T, D>>::value;
+
 // lds <- sgn * (-i) * c * H_k  (sgn = +1: A_k / 2^s with c = dt / 2^s;
 // sgn = -1: A_k^dag / 2^s).  H_k = H0 + sum_j u[j][k] Hc[j] in precision T.
 template <typename T, int D, typename Ops, int G = 1>
@@ -260,7 +267,49 @@ __device__ __forceinline__ void assemble(void* lds, const ProbDesc& P, int k, do
     hi[v] = Prec<T>::gld4(H + D * D + e0 + 4 * NT * v);
   }
   const size_t tab_bytes = (size_t)P.m * D * (sizeof(int) + 2 * sizeof(T)) + (size_t)P.m * sizeof(T);
-  if (mono && tab_bytes <= (size_t)Ops::BYTES) {
+  if (mono && D >= 32 && !ct && kStdLds<T, D, Ops>) {
+    // Scatter form (D >= 32, where the expm is the only row-table caller):
+    // H0 goes to LDS unscaled; thread a < D then adds u_j Hc[j][a][col_j(a)]
+    // to entry (a, col_j(a)) of its own row for j = 0 ... m - 1 (the dense
+    // sum's nonzero terms in its order, so H_k is the same); every thread
+    // then reads its chunks back.  O(m D) work instead of every thread
+    // scanning every control for its chunks.
+    T* pl = static_cast<T*>(lds);
+    T* pi = pl + D * Mat<T, D>::SD;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int e = e0 + 4 * NT * v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int off = lds_off<T, D>(e / D, e % D + i);
+        pl[off] = hr[v][i];
+        pi[off] = hi[v][i];
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < D) {
+      const int a = threadIdx.x;
+      const T* mv = reinterpret_cast<const T*>(P.mval);
+      for (int j = 0; j < P.m; ++j) {
+        const size_t idx = (size_t)j * D + a;
+        const T uj = (T)gp(P.u)[(size_t)j * P.N + k];
+        const int off = lds_off<T, D>(a, gp(P.mcol)[idx]);
+        pl[off] = fma(uj, gp(mv)[2 * idx], pl[off]);
+        pi[off] = fma(uj, gp(mv)[2 * idx + 1], pi[off]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int e = e0 + 4 * NT * v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int off = lds_off<T, D>(e / D, e % D + i);
+        hr[v][i] = pl[off];
+        hi[v][i] = pi[off];
+      }
+    }
+  } else if (mono && tab_bytes <= (size_t)Ops::BYTES) {
     // The problem's row tables and the slice's amplitudes go through LDS (the
     // left-factor space, written below only after a barrier): one round trip
     // of coalesced loads instead of one per group of controls.
