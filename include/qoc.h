@@ -76,7 +76,10 @@ typedef struct {
                              at d > 16); 0 = no limit.
                              When those arrays exceed it, slices are
                              processed in checkpoint segments and recomputed
-                             for the gradient pass (same results, more work). */
+                             for the gradient pass (same results, more work).
+                             The floor is one chunk of slices per segment plus
+                             the per-chunk arrays: a smaller budget is raised to
+                             it (qoc_workspace_size reports the actual size). */
   double reunitarise_tol; /* reduced precision: every chunk product S of the
                              scans is checked in FP64, r = |S^dag S - I|_F, and gets one
                              Newton-Schulz step S (3I - S^dag S)/2 when r exceeds it.
