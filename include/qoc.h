@@ -57,9 +57,10 @@ typedef enum {
 typedef enum {
   QOC_FP64 = 0,  /* complex128 GEMMs on FP64 MFMA */
   QOC_FP32 = 1,  /* complex64 GEMMs on FP32 MFMA; norms, traces and inner products in FP64 */
-  QOC_BF16X3 = 2 /* complex products as three split-BF16 MFMA products (hi*hi + hi*lo +
-                    lo*hi) with FP32 accumulation and FP32 storage; FP64 norms, traces
-                    and inner products; 17 <= d <= 64 */
+  QOC_BF16X3 = 2 /* the adjoint's complex products (the Frechet series and its traces)
+                    as three split-BF16 MFMA products (hi*hi + hi*lo + lo*hi) with FP32
+                    accumulation; propagators, scans and carries as QOC_FP32; FP32
+                    storage; FP64 norms, traces and inner products; 17 <= d <= 64 */
 } qoc_precision;
 
 typedef struct {

@@ -540,15 +540,17 @@ __device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel
 }
 
 // Gradient from Z = Z_k: T_j = Tr(Z^dag Hc[j]) with FP64 accumulation and
-// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  Controls are taken kEpiGroup
-// at a time: every lane forms its partial sums for the whole group (the
-// group's loads are independent, so their latencies overlap), one
-// multi-value wavefront reduction combines them, one barrier publishes the
-// per-wavefront totals and one thread per control adds those up.  Control
-// indices past the last one are clamped to it, so every load stays in bounds
-// and the surplus sums are discarded.  red: 2 x 2 kEpiGroup x (threads / 64)
-// doubles of LDS (double-buffered by group).
+// grad[j][k] = (2 dt / d^2) Im(conj(g) T_j).  Controls are taken in groups
+// (kEpiGroup, or kEpiDense for the FP32 dense controls): every lane forms
+// its partial sums for the whole group, one multi-value wavefront reduction
+// combines them, one barrier publishes the per-wavefront totals and one
+// thread per control adds those up.  Control indices past the last one are
+// clamped to it, so every load stays in bounds, and their sums are
+// discarded.  red: 2 x 2 G x (threads / 64) doubles of LDS for groups of G
+// (double-buffered by group).
 constexpr int kEpiGroup = 4;
+// Controls reduced together by the FP32 dense-control epilogue.
+constexpr int kEpiDense = 16;
 
 // Stores the gradient entry (j, k) from T_j = a + i b.
 __device__ __forceinline__ void grad_put(const ProbDesc& P, int j, int k, double a, double b) {
@@ -563,12 +565,12 @@ __device__ __forceinline__ void grad_put(const ProbDesc& P, int j, int k, double
   }
 }
 
-template <int NWAVES>
-__device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j0, int grp, double (&v)[2 * kEpiGroup],
+template <int NWAVES, int G = kEpiGroup>
+__device__ __forceinline__ void epilogue_publish(const ProbDesc& P, int k, int j0, int grp, double (&v)[2 * G],
                                                  const Lane& L, double* red) {
-  constexpr int V = 2 * kEpiGroup;
+  constexpr int V = 2 * G;
   constexpr int SH = 6 - __builtin_ctz(V);
-  const int nj = min(kEpiGroup, P.m - j0);
+  const int nj = min(G, P.m - j0);
   const double t = wave_sum_many<V>(v, L.lane);
   double* rg = red + (grp & 1) * V * NWAVES;
   if ((L.lane & ((1 << SH) - 1)) == 0) rg[(L.lane >> SH) * NWAVES + L.w] = t;
@@ -652,13 +654,23 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
       zr[4 * q + i] = (double)zl[off];
       zi[4 * q + i] = (double)zl[D * SD + off];
     }
-  // controls whose row segments are loaded together (register budget)
-  constexpr int LG = sizeof(T) == 4 ? kEpiGroup : 2;
+  // FP32 keeps the sums of kEpiDense controls together for one multi-value
+  // reduction and one barrier; FP64 (whose values take twice the registers)
+  // publishes every kEpiGroup controls.  LG controls' row segments are
+  // loaded together.
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int JG = F32 ? kEpiDense : kEpiGroup;
+  constexpr int LG = 2;
   const T* H = reinterpret_cast<const T*>(P.Hint);
-  for (int j0 = 0, grp = 0; j0 < P.m; j0 += kEpiGroup, ++grp) {
-    double v[2 * kEpiGroup];
+  for (int j0 = 0, grp = 0; j0 < P.m; j0 += JG, ++grp) {
+    double v[2 * JG];
 #pragma unroll
-    for (int jb = 0; jb < kEpiGroup; jb += LG) {
+    for (int jb = 0; jb < JG; jb += LG) {
+      if (F32 && j0 + jb >= P.m) {  // past the last control: nothing to load
+#pragma unroll
+        for (int jj = 0; jj < LG; ++jj) v[2 * (jb + jj)] = v[2 * (jb + jj) + 1] = 0.0;
+        continue;
+      }
       v4 hr[LG][NV], hi[LG][NV];
 #pragma unroll
       for (int jj = 0; jj < LG; ++jj) {
@@ -686,7 +698,7 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
         v[2 * (jb + jj) + 1] = ti;
       }
     }
-    epilogue_publish<D / 16>(P, k, j0, grp, v, L, red);
+    epilogue_publish<D / 16, JG>(P, k, j0, grp, v, L, red);
   }
 }
 
@@ -1043,7 +1055,7 @@ __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves
 void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
-  __shared__ double red[2 * kEpiGroup * 2 * NW];
+  __shared__ double red[2 * kEpiDense * 2 * NW];
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -1972,13 +1984,17 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
       break;
     }
     case ST_EXPM: {
+      // the split-BF16 policy serves the adjoint only (launch_stage)
+      if constexpr (kStdLds<T, D, Ops>) {
       Work w = L.dyn ? dyn : slice_work(L, rg);
       if (L.dyn) hipLaunchKernelGGL((k_expm<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
       else hipLaunchKernelGGL((k_expm<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      }
       break;
     }
     case ST_SCAN:
     case ST_BSCAN: {
+      if constexpr (kStdLds<T, D, Ops>) {
       Work w = L.dyn ? dyn : chunk_work(L, rg);
       // a recompute sweep runs the forward and backward passes of a segment
       // together (they are independent once mc is known)
@@ -1987,6 +2003,7 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
       const dim3 grid(grid_of(L, w.total, 0), both ? 2 : 1);
       if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), grid, dim3(NT), 0, st, w, dir);
       else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), grid, dim3(NT), 0, st, w, dir);
+      }
       break;
     }
     case ST_CARRY: {

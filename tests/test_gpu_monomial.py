@@ -40,6 +40,23 @@ def test_monomial_controls_match_the_oracle(gpu_lib, prec, d, m, N):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("d,m", [(16, 20), (40, 24), (64, 20)])
+def test_many_row_table_controls(gpu_lib, prec, d, m):
+    """More controls than the d = 16 table staging holds (the gathered
+    fall-back there) and, at d >= 32, many controls added row by row in
+    order, several of them on the same entry of a row."""
+    from paper_2208_12187_amd import qoc
+
+    p = make_random_monomial(9, d, m, 30, dt=0.05)
+    print(f"[monomial] many controls d={d} m={m} {prec}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec)
+    _check(p, prec, F, grad, ref)
+    Fd, gd = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec, dense_controls=True)
+    assert abs(F - Fd) <= 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("cfg,N", [(2, 300), (3, 240), (4, 40)])
 def test_spin_chain_row_tables_against_dense_kernels(gpu_lib, prec, cfg, N):
     """The spin-chain controls are Pauli strings: the row-table path and the

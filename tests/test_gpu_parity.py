@@ -115,6 +115,22 @@ def test_non_power_of_two_dimensions_are_padded_exactly(gpu_lib, d):
     _check(F, grad, ref, "fp64")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_dimensional_problem(gpu_lib, prec):
+    """d = 1: every U_k is a phase, so F = 1 and the gradient vanishes
+    (padded to 16 like any small d)."""
+    from paper_2208_12187_amd import qoc
+
+    rng = np.random.default_rng(41)
+    p = Problem(np.array([[0.7]], dtype=complex), np.array([[[1.0]], [[-0.4]]], dtype=complex),
+                rng.normal(0, 0.5, (2, 17)), 0.03, np.array([[np.exp(0.3j)]]))
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(ref["F"] - 1.0) <= 1e-14 and np.max(np.abs(ref["grad"])) <= 1e-14
+    assert abs(F - 1.0) <= tol and np.max(np.abs(grad)) <= tol
+
+
 @pytest.mark.parametrize("N", [1, 2])
 def test_tiny_slice_counts(gpu_lib, N):
     from paper_2208_12187_amd import qoc
