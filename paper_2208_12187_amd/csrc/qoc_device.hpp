@@ -501,8 +501,13 @@ __device__ __forceinline__ double wave_sum_many(double (&v)[V], int lane) {
     const bool up = (lane & o) != 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      const double keep = up ? v[i + H] : v[i];
-      const double give = up ? v[i] : v[i + H];
+      double lo = v[i], hi = v[i + H];
+      // opaque to the optimiser: the selects below stay selects of values
+      // (folded into one load through a selected address, they would keep
+      // the array in scratch memory)
+      asm volatile("" : "+v"(lo), "+v"(hi));
+      const double keep = up ? hi : lo;
+      const double give = up ? lo : hi;
       v[i] = keep + __shfl_xor(give, o, 64);
     }
   }
@@ -526,8 +531,13 @@ __device__ __forceinline__ double group_sum_many(double (&v)[V], int lane) {
     const bool up = (lane & o) != 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      const double keep = up ? v[i + H] : v[i];
-      const double give = up ? v[i] : v[i + H];
+      double lo = v[i], hi = v[i + H];
+      // opaque to the optimiser: the selects below stay selects of values
+      // (folded into one load through a selected address, they would keep
+      // the array in scratch memory)
+      asm volatile("" : "+v"(lo), "+v"(hi));
+      const double keep = up ? hi : lo;
+      const double give = up ? lo : hi;
       v[i] = keep + __shfl_xor(give, o, 64);
     }
   }

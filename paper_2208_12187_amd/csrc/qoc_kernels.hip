@@ -550,7 +550,7 @@ __device__ __forceinline__ void residual_epilogue(const ProbDesc& P, const Panel
 // (double-buffered by group).
 constexpr int kEpiGroup = 4;
 // Controls reduced together by the FP32 dense-control epilogue.
-constexpr int kEpiDense = 16;
+constexpr int kEpiDense = 8;
 
 // Stores the gradient entry (j, k) from T_j = a + i b.
 __device__ __forceinline__ void grad_put(const ProbDesc& P, int j, int k, double a, double b) {
@@ -666,36 +666,37 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
     double v[2 * JG];
 #pragma unroll
     for (int jb = 0; jb < JG; jb += LG) {
-      if (F32 && j0 + jb >= P.m) {  // past the last control: nothing to load
+      double tr[LG], ti[LG];
 #pragma unroll
-        for (int jj = 0; jj < LG; ++jj) v[2 * (jb + jj)] = v[2 * (jb + jj) + 1] = 0.0;
-        continue;
-      }
-      v4 hr[LG][NV], hi[LG][NV];
+      for (int jj = 0; jj < LG; ++jj) tr[jj] = ti[jj] = 0.0;
+      if (!F32 || j0 + jb < P.m) {  // (FP32 groups: nothing to load past the last control)
+        v4 hr[LG][NV], hi[LG][NV];
 #pragma unroll
-      for (int jj = 0; jj < LG; ++jj) {
-        const int j = min(j0 + jb + jj, P.m - 1);
-        const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
+        for (int jj = 0; jj < LG; ++jj) {
+          const int j = min(j0 + jb + jj, P.m - 1);
+          const T* Hj = H + (size_t)(j + 1) * 2 * D * D + e0;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-          hr[jj][q] = Prec<T>::gld4(Hj + 4 * NT * q);
-          hi[jj][q] = Prec<T>::gld4(Hj + D * D + 4 * NT * q);
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < LG; ++jj) {
-        double tr = 0, ti = 0;
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const double a = zr[4 * q + i], b = zi[4 * q + i];
-            const double x = (double)hr[jj][q][i], y = (double)hi[jj][q][i];
-            tr += a * x + b * y;  // conj(z) h
-            ti += a * y - b * x;
+          for (int q = 0; q < NV; ++q) {
+            hr[jj][q] = Prec<T>::gld4(Hj + 4 * NT * q);
+            hi[jj][q] = Prec<T>::gld4(Hj + D * D + 4 * NT * q);
           }
-        v[2 * (jb + jj)] = tr;
-        v[2 * (jb + jj) + 1] = ti;
+        }
+#pragma unroll
+        for (int jj = 0; jj < LG; ++jj)
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double a = zr[4 * q + i], b = zi[4 * q + i];
+              const double x = (double)hr[jj][q][i], y = (double)hi[jj][q][i];
+              tr[jj] += a * x + b * y;  // conj(z) h
+              ti[jj] += a * y - b * x;
+            }
+      }
+#pragma unroll
+      for (int jj = 0; jj < LG; ++jj) {
+        v[2 * (jb + jj)] = tr[jj];
+        v[2 * (jb + jj) + 1] = ti[jj];
       }
     }
     epilogue_publish<D / 16, JG>(P, k, j0, grp, v, L, red);
