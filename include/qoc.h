@@ -151,6 +151,15 @@ size_t qoc_workspace_size(int B, int d, int m, int N, int precision, int chunk, 
  */
 int qoc_default_chunk(int d, int N);
 
+/*
+ * Slices per scan chunk that the serving engine uses for a request:
+ * ceil(sqrt(N / 8)), shorter than the default because a tick holds few
+ * problems and the chain of dependent products then bounds a request's
+ * latency.  A host or device call with opt->chunk set to it returns the
+ * engine's results bit for bit.  0 for d outside [1, 128] or N < 1.
+ */
+int qoc_engine_chunk(int d, int N);
+
 int qoc_propagate_dev(int B, int d, int m, int N, const void* H0, const void* Hc,
                       const void* u, double dt, void* U_total, void* workspace,
                       size_t ws_bytes, const qoc_options* opt);

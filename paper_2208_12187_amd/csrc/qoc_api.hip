@@ -456,6 +456,11 @@ int qoc_gradient(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const do
                   qoc::RUN_FID | qoc::RUN_BWD | qoc::RUN_GRAD);
 }
 
+int qoc_engine_chunk(int d, int N) {
+  if (d < 1 || d > 128 || N < 1) return 0;
+  return qoc::engine_chunk(N);
+}
+
 int qoc_default_chunk(int d, int N) {
   if (d < 1 || d > 128 || N < 1) return 0;
   return qoc::default_chunk(qoc::padded_dim(d), N);

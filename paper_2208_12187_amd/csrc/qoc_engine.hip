@@ -160,8 +160,9 @@ size_t input_bytes(int d, int m, int N) { return (size_t)d * d * 16 * (m + 2) + 
 
 // Device bytes of one request: inputs, F and gradient, and its workspace.
 Layout request_layout(int precision, int d, int m, int N) {
-  // one problem, no descriptor table; D = 128 scratch is held by the engine
-  Layout lo = make_layout(1, d, m, N, precision, 0, 0);
+  // one problem, no descriptor table; D = 128 scratch is held by the engine;
+  // the latency chunk length
+  Layout lo = make_layout(1, d, m, N, precision, engine_chunk(N), 0);
   return lo;
 }
 

@@ -38,6 +38,7 @@ EXPORTS = (
     "qoc_gradient",
     "qoc_workspace_size",
     "qoc_default_chunk",
+    "qoc_engine_chunk",
     "qoc_propagate_dev",
     "qoc_fidelity_dev",
     "qoc_gradient_dev",
@@ -111,6 +112,8 @@ def lib() -> ctypes.CDLL:
     L.qoc_workspace_size.restype = sz
     L.qoc_default_chunk.argtypes = [i32, i32]
     L.qoc_default_chunk.restype = i32
+    L.qoc_engine_chunk.argtypes = [i32, i32]
+    L.qoc_engine_chunk.restype = i32
     L.qoc_propagate_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, sz, opt]
     L.qoc_fidelity_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, sz, opt]
     L.qoc_gradient_dev.argtypes = [i32, i32, i32, i32, vp, vp, vp, dbl, vp, vp, vp, vp, sz, opt]
@@ -260,6 +263,14 @@ def slice_plan(H0, Hc, u, dt, precision="fp64", with_gradient=True) -> np.ndarra
 def default_chunk(d, N) -> int:
     """Slices per scan chunk when the chunk option is 0."""
     n = lib().qoc_default_chunk(d, N)
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+def engine_chunk(d, N) -> int:
+    """Slices per scan chunk the serving engine uses for a request."""
+    n = lib().qoc_engine_chunk(d, N)
     if n == 0:
         _check(-1)
     return int(n)

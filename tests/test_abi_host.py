@@ -76,6 +76,10 @@ def test_default_chunk():
     assert qoc.default_chunk(128, 1000) == 32 and qoc.default_chunk(100, 2000) == 45
     L = qoc.lib()
     assert L.qoc_default_chunk(0, 10) == 0 and L.qoc_default_chunk(129, 10) == 0 and L.qoc_default_chunk(8, 0) == 0
+    # the serving engine's latency chunk: ceil(sqrt(N / 8)), shorter than the default
+    assert qoc.engine_chunk(64, 2000) == 16 and qoc.engine_chunk(128, 1000) == 12 and qoc.engine_chunk(2, 1) == 1
+    assert all(qoc.engine_chunk(d, N) <= qoc.default_chunk(d, N) for d in (2, 16, 64, 128) for N in (1, 7, 100, 2000))
+    assert L.qoc_engine_chunk(0, 10) == 0 and L.qoc_engine_chunk(129, 10) == 0 and L.qoc_engine_chunk(8, 0) == 0
 
 
 def test_workspace_size_scales_with_batch_and_precision():

@@ -110,5 +110,5 @@ def test_engine_uses_the_same_path_as_the_host_entry(gpu_lib):
             out[ids[rid]] = (F, eng.fetch(rid))
     eng.close()
     for i, p in enumerate(probs):
-        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32")
+        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", chunk=qoc.engine_chunk(p.d, p.N))
         assert out[i][0] == F_api and np.array_equal(out[i][1], g_api)

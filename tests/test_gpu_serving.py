@@ -40,7 +40,7 @@ def test_engine_mix_equals_alone_and_api(gpu_lib, prec):
     alone = _run(one, probs)
     one.close()
     for i, p in enumerate(probs):
-        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec)
+        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, prec, chunk=qoc.engine_chunk(p.d, p.N))
         assert mix[i][0] == alone[i][0] == F_api, (i, mix[i][0], alone[i][0], F_api)
         assert np.array_equal(mix[i][1], alone[i][1])
         assert np.array_equal(mix[i][1], g_api)
@@ -70,7 +70,7 @@ def test_engine_admission_with_a_small_pool(gpu_lib):
     res = _run(eng, probs)
     eng.close()
     for (F, g), p in zip(res, probs):
-        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32")
+        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", chunk=qoc.engine_chunk(p.d, p.N))
         assert F == F_api and np.array_equal(g, g_api)
 
 
