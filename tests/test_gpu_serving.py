@@ -46,6 +46,28 @@ def test_engine_mix_equals_alone_and_api(gpu_lib, prec):
         assert np.array_equal(mix[i][1], g_api)
 
 
+def test_split_bf16_engine(gpu_lib):
+    """A split-BF16 engine serves 17 <= d <= 64 (other d are refused at
+    submit) and gives the host entry point's results bit for bit, within the
+    gates of the oracle."""
+    from paper_2208_12187_amd import qoc
+
+    probs = [make_request(i, d, N, trace_seed=17) for i, (d, N) in enumerate([(32, 210), (64, 95), (32, 17)])]
+    eng = qoc.Engine("bf16x3", pool_bytes=4 << 30, host_bytes=1 << 28, max_active=8)
+    small = make_request(9, 16, 30, trace_seed=17)
+    with pytest.raises(qoc.QocError) as e:
+        eng.submit(small.H0, small.Hc, small.u, small.dt, small.V)
+    assert e.value.code == -6
+    res = _run(eng, probs)
+    eng.close()
+    for (F, g), p in zip(res, probs):
+        F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "bf16x3", chunk=qoc.engine_chunk(p.d, p.N))
+        assert F == F_api and np.array_equal(g, g_api)
+        ref = oracle.grape_ref(p)
+        assert abs(F - ref["F"]) <= 1e-5
+        assert np.max(np.abs(g - ref["grad"])) <= 1e-4 * np.max(np.abs(ref["grad"]))
+
+
 def test_engine_fp64_matches_oracle(gpu_lib):
     from paper_2208_12187_amd import qoc
 
