@@ -720,6 +720,11 @@ constexpr int kMinWaves = D >= 32 ? 2 : 1;
 template <int D>
 constexpr bool kKeepH = D >= 32;
 
+// The expm's products take their steps in pairs (cgemm3m) in FP32; in FP64
+// the extra fragment registers would add to its spills.
+template <typename T>
+constexpr int kExpmPairs = sizeof(T) == 4 ? 2 : 1;
+
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
 void k_expm(Work W) {
@@ -741,19 +746,19 @@ void k_expm(Work W) {
     panel_scale(R, (T)(1.0 / q));
     panel_add_identity(R, L, (T)1);
     for (int i = q - 1; i >= 2; --i) {
-      Ops::gemm3(acc, lds, R, L, true);
+      Ops::template gemm3<kExpmPairs<T>>(acc, lds, R, L, true);
       R = acc;
       panel_scale(R, (T)(1.0 / i));
       panel_add_identity(R, L, (T)1);
     }
-    Ops::gemm3(acc, lds, R, L, true);
+    Ops::template gemm3<kExpmPairs<T>>(acc, lds, R, L, true);
     R = acc;
   }
   for (int j = 0; j < s; ++j) {
     __syncthreads();
     Ops::store(lds, R, L);
     __syncthreads();
-    Ops::gemm3(acc, lds, R, L, true);
+    Ops::template gemm3<kExpmPairs<T>>(acc, lds, R, L, true);
     panel_axpby(R, (T)1, acc, (T)2);
   }
   panel_store(pf_mat<T, D>(P.delta, k - W.rg.kbase), R, L);
