@@ -34,8 +34,9 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     complex product ("adjoint_8d3").
 
     Complex d x d products per slice: expm q - 1 + s; scans one per
-    direction; adjoint 3 (qb + s) - 3 (one for W, three per block Horner
-    step or squaring, less the top-left blocks the last step does not need).
+    direction; adjoint 6 + 3 floor((qb - 3) / 2) + 3 s (one for W, three for
+    the square of the block, three per Paterson-Stockmeyer step with a matrix
+    digit, two for the last step's top-right block, three per squaring).
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
     the three-product (Gauss) form.  FP32 and FP64 use the latter in every
     stage at 32 <= d <= 64, and FP32 also in the expm and adjoint at d = 128.
@@ -50,7 +51,7 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     g_adj = 24.0 * d ** 3 if prec == "bf16x3" else (G3 if (mid or big32) else G4)
     g_expm = G3 if (mid or big32) else G4
     g_scan = G3 if mid else G4
-    n_adj = 3 * (qb + s) - 3
+    n_adj = 6 + 3 * np.maximum(0, (qb - 3) // 2) + 3 * s
     return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * g_scan * len(s)),
             "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
 

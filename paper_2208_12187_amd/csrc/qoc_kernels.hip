@@ -1041,9 +1041,9 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 // One workgroup per slice.
 //  1. W_k = bloc[k] xprev[k]^dag  (one product; bloc[k] carries mc[c]).
 //  2. X = A_k^dag / 2^s in LDS buffer 0, E = W_k / 2^s in buffer 1.
-//  3. Block Horner of degree qb on M = [[X, E], [0, X]] in delta form:
-//     R = [[R1, R2], [0, R1]], R_qb = I + M/qb, R_i = I + M R_{i+1} / i, and
-//     M R = [[X R1, X R2 + E R1], [0, X R1]].  Delta block = M R_2.
+//  3. The Taylor polynomial of degree qb of M = [[X, E], [0, X]] in delta
+//     form, p(M) - I, by Paterson-Stockmeyer with M^2 as the step: the top
+//     right block of exp(M) is the Frechet derivative L(X, E).
 //  4. s squarings: [[I + D1, Q], [0, I + D1]]^2 gives D1 <- 2 D1 + D1^2 and
 //     Q <- 2Q + D1 Q + Q D1.  Z_k = Q.
 //  5. T_j = Tr(Z_k^dag Hc[j]) in FP64, grad = (2 dt / d^2) Im(conj(g) T_j).
@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 // loaded together with the W factors where the extra registers cost no
 // occupancy (FP32 at D = 64, FP64 at D = 32).
 template <typename T, int D>
-constexpr int kAdjWaves = (sizeof(T) == 4 && D <= 64) ? 2 : 1;
+constexpr int kAdjWaves = ((sizeof(T) == 4 && D <= 64) || (sizeof(T) == 8 && D == 32)) ? 2 : 1;
 template <typename T, int D>
 constexpr bool kEarlyH = (sizeof(T) == 4 && D == 64) || (sizeof(T) == 8 && D == 32);
 
@@ -1102,25 +1102,60 @@ void k_adjoint(Work W) {
   const void* X = lds[0];
   const void* E = lds[1];
 
-  // 3. Horner on the block
-  Ops::load(R1, X, L);
-  panel_scale(R1, (T)(1.0 / qb));
-  panel_add_identity(R1, L, (T)1);
-  panel_scale(R2, (T)(1.0 / qb));
-  for (int i = qb - 1; i >= 2; --i) {
-    Ops::gemm3(A2, X, R2, L, true);
-    Ops::gemm3(A2, E, R1, L, false);
-    Ops::gemm3(A1, X, R1, L, true);
-    const T inv = (T)(1.0 / i);
-    R1 = A1;
-    panel_scale(R1, inv);
-    panel_add_identity(R1, L, (T)1);
-    R2 = A2;
-    panel_scale(R2, inv);
-  }
+  // 3. Paterson-Stockmeyer on the block.  With M^2 = [[X2, S], [0, X2]],
+  //    X2 = X X and S = X E + E X, the delta block is p(M) - I = M + M^2 C,
+  //    C = sum_{n=2..qb} M^(n-2) / n!.  C runs Horner in M^2 over the digits
+  //    D_t = I / (2t+2)! + M / (2t+3)! (terms above degree qb dropped):
+  //    C <- D_t + M^2 C = [[D_t11 + X2 C1, b_t E + X2 C2 + S C1], [0, .]].
+  //    Each block product by M^2 takes three d x d products, the last one
+  //    only the blocks used next.
+  Panel<T, D> R3;
+  Ops::load(R1, X, L);              // R1 = X, R2 = E
+  Ops::gemm3(A1, X, R1, L, true);   // A1 = X2
   Ops::gemm3(A2, X, R2, L, true);
-  Ops::gemm3(A2, E, R1, L, false);  // A2 = Q (top-right of the delta block)
-  if (s > 0) Ops::gemm3(A1, X, R1, L, true);  // A1 = D1 (top-left)
+  Ops::gemm3(A2, E, R1, L, false);  // A2 = S
+  __syncthreads();                  // X and E are read: M^2 takes their place
+  Ops::store(lds[0], A1, L);
+  Ops::store(lds[1], A2, L);
+  const int top = (qb - 2) / 2;  // index of the last digit
+  int t;                         // next digit, folded in by a block product
+  if (qb & 1) {                  // C = D_top = I / (qb-1)! + M / qb!
+    t = top - 1;
+    A1 = R1;
+    panel_scale(A1, (T)inv_factorial(qb));
+    panel_add_identity(A1, L, (T)inv_factorial(qb - 1));
+    A2 = R2;
+    panel_scale(A2, (T)inv_factorial(qb));
+  } else if (top > 0) {  // D_top = I / qb!: C = D_{top-1} + M^2 / qb! without a product
+    t = top - 2;
+    panel_axpby(A1, (T)inv_factorial(qb - 1), R1, (T)inv_factorial(qb));
+    panel_add_identity(A1, L, (T)inv_factorial(qb - 2));
+    panel_axpby(A2, (T)inv_factorial(qb - 1), R2, (T)inv_factorial(qb));
+  } else {  // qb = 2: C = I / 2
+    t = -1;
+    panel_zero(A1);
+    panel_add_identity(A1, L, (T)0.5);
+    panel_zero(A2);
+  }
+  __syncthreads();
+  for (; t >= 0; --t) {
+    const T a = (T)inv_factorial(2 * t + 2), b = (T)inv_factorial(2 * t + 3);
+    R3 = R2;
+    panel_scale(R3, b);
+    Ops::gemm3(R3, lds[0], A2, L, false);
+    Ops::gemm3(R3, lds[1], A1, L, false);  // R3 = b E + X2 C2 + S C1
+    A2 = R1;
+    panel_scale(A2, b);
+    panel_add_identity(A2, L, a);
+    Ops::gemm3(A2, lds[0], A1, L, false);  // A2 = a I + b X + X2 C1
+    A1 = A2;
+    A2 = R3;
+  }
+  Ops::gemm3(R2, lds[0], A2, L, false);
+  Ops::gemm3(R2, lds[1], A1, L, false);              // R2 = Q = E + X2 C2 + S C1
+  if (s > 0) Ops::gemm3(R1, lds[0], A1, L, false);  // R1 = D1 = X + X2 C1
+  A1 = R1;
+  A2 = R2;
 
   // 4. squarings
   for (int j = 0; j < s; ++j) {
@@ -1893,44 +1928,81 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     // W = bloc[k] xprev[k]^dag (bloc carries mc[c])
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k - W.rg.kbase), L);
     gemm128<T, false, k128Gauss<T>>(acc, lds, pf_mat<T, 128>(P.bloc, k - W.rg.kbase), S0, L, true);
-    // E = W / 2^s, R2 = E / qb
+    // E = W / 2^s
     panel_scale(acc, (T)ldexp(1.0, -s));
     panel_store(SE, acc, L);
-    panel_scale(acc, (T)(1.0 / qb));
-    panel_store(SR2, acc, L);
     // X = A^dag / 2^s: the expm pass's A / 2^s negated (A = -i dt H_k with H_k
     // Hermitian), or its conjugate transpose for general generators (own
     // panel; the barrier at the start of the next product publishes SX)
     if (P.flags & RUN_GENERAL) {
       transpose128<T>(SX, lds, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
-      panel_load(acc, SX, L);
     } else {
       panel_load(acc, pf_mat<T, 128>(P.hk, k - W.rg.kbase), L);
       panel_scale(acc, (T)-1);
       panel_store(SX, acc, L);
     }
-    // R1 = I + X / qb
-    panel_scale(acc, (T)(1.0 / qb));
-    panel_add_identity(acc, L, (T)1);
-    panel_store(SR1, acc, L);
-    for (int i = qb - 1; i >= 2; --i) {
-      const T inv = (T)(1.0 / i);
-      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR2, L, true);
-      gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SR1, L, false);
-      panel_scale(acc, inv);
-      panel_store(SR2, acc, L);  // R2 <- (X R2 + E R1) / i  (own panel; R1 still intact)
-      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR1, L, true);
-      panel_scale(acc, inv);
-      panel_add_identity(acc, L, (T)1);
+    // The block polynomial by Paterson-Stockmeyer as in k_adjoint: M^2 =
+    // [[X2, S], [0, X2]] into S0 (X2) and S1 (S), the running C = [[C1, C2],
+    // [0, C1]] in SR1 and SR2.
+    gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SX, L, true);
+    panel_store(S0, acc, L);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SE, L, true);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SX, L, false);
+    panel_store(S1, acc, L);
+    const int top = (qb - 2) / 2;
+    int t;
+    if (qb & 1) {  // C = I / (qb-1)! + M / qb!
+      t = top - 1;
+      panel_load(acc, SX, L);
+      panel_scale(acc, (T)inv_factorial(qb));
+      panel_add_identity(acc, L, (T)inv_factorial(qb - 1));
+      panel_store(SR1, acc, L);
+      panel_load(acc, SE, L);
+      panel_scale(acc, (T)inv_factorial(qb));
+      panel_store(SR2, acc, L);
+    } else if (top > 0) {  // C = I / (qb-2)! + M / (qb-1)! + M^2 / qb!
+      t = top - 2;
+      panel_load(acc, SX, L);
+      panel_scale(acc, (T)inv_factorial(qb - 1));
+      panel_axpy_pf(acc, (T)inv_factorial(qb), S0, L);
+      panel_add_identity(acc, L, (T)inv_factorial(qb - 2));
+      panel_store(SR1, acc, L);
+      panel_load(acc, SE, L);
+      panel_scale(acc, (T)inv_factorial(qb - 1));
+      panel_axpy_pf(acc, (T)inv_factorial(qb), S1, L);
+      panel_store(SR2, acc, L);
+    } else {  // qb = 2: C = I / 2
+      t = -1;
+      panel_zero(acc);
+      panel_store(SR2, acc, L);
+      panel_add_identity(acc, L, (T)0.5);
       panel_store(SR1, acc, L);
     }
-    // D1 = X R1 (into S1) when squaring follows; Q = X R2 + E R1 (into S0 and acc)
-    if (s > 0) {
-      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR1, L, true);
-      panel_store(S1, acc, L);
+    for (; t >= 0; --t) {  // C <- D_t + M^2 C (own panels of SR1, SR2 only)
+      const T a = (T)inv_factorial(2 * t + 2), b = (T)inv_factorial(2 * t + 3);
+      panel_load(acc, SE, L);
+      panel_scale(acc, b);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S1, SR1, L, false);
+      panel_store(SR2, acc, L);  // b E + X2 C2 + S C1
+      panel_load(acc, SX, L);
+      panel_scale(acc, b);
+      panel_add_identity(acc, L, a);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR1, L, false);
+      panel_store(SR1, acc, L);  // a I + b X + X2 C1
     }
-    gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SR2, L, true);
-    gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SR1, L, false);
+    // Q = E + X2 C2 + S C1 and, when squaring follows, D1 = X + X2 C1 (into
+    // S1 once every wavefront has staged S; Q waits in the own panel of SE).
+    panel_load(acc, SE, L);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, S1, SR1, L, false);
+    if (s > 0) {
+      panel_store(SE, acc, L);
+      panel_load(acc, SX, L);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR1, L, false);
+      panel_store(S1, acc, L);
+      panel_load(acc, SE, L);
+    }
     for (int j = 0; j < s; ++j) {
       panel_store(S0, acc, L);                        // Q
       gemm128<T, false, k128Gauss<T>>(acc, lds, S1, S0, L, true);   // D1 Q

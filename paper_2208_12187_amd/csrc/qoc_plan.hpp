@@ -15,7 +15,7 @@
 // Among s in [s0, s0 + 6], s0 = least s >= 0 with r <= 1, the value that
 // minimises the number of complex d x d products of the path is taken:
 //    exp:       (q - 1) + s
-//    gradient:  + 3 (qb - 2) + 2 + 3 s    (block Horner, final step, squarings)
+//    gradient:  + frechet_products(qb) + 3 s   (block polynomial, squarings)
 #pragma once
 
 #include <math.h>
@@ -52,9 +52,22 @@ QOC_HD inline int frechet_degree(double r, double ur) {
   return qb;
 }
 
+QOC_HD inline double inv_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f /= i;
+  return f;
+}
+
+// Complex d x d products of the degree-qb Taylor polynomial of the block
+// [[X, E], [0, X]] by Paterson-Stockmeyer with the block's square as the
+// step: three for the square, three per Horner step in the square that has a
+// matrix digit (floor((qb - 3) / 2) of them), two for the last step's top
+// right block (the top left one is counted with the squarings).
+QOC_HD inline int frechet_products(int qb) { return 5 + 3 * (qb > 3 ? (qb - 3) / 2 : 0); }
+
 QOC_HD inline int plan_cost(int s, int q, int qb, bool grad) {
   int cost = q - 1 + s;
-  if (grad) cost += 3 * (qb - 2) + 2 + 3 * s;
+  if (grad) cost += frechet_products(qb) + 3 * s;
   return cost;
 }
 

@@ -1,5 +1,5 @@
 """Host-side checks of the bench's flop accounting: the per-slice product
-counts follow the kernels' Horner and squaring loops, and the three-product
+counts follow the kernels' polynomial and squaring loops, and the three-product
 form is counted only where the kernels use it."""
 import numpy as np
 
@@ -7,11 +7,19 @@ import bench
 
 
 def _products_adjoint(s, qb):
-    # W = bloc xprev^dag: one product; block Horner from degree qb: three
-    # products per step, the last step without the top-left block unless
-    # squarings follow; each squaring three, the last without the top-left
-    # block.
-    n = 1 + 3 * (qb - 2) + 2 + (1 if s > 0 else 0)
+    # W = bloc xprev^dag: one product.  Block polynomial by Paterson-Stockmeyer
+    # in M^2: three products for M^2; the digits above the first one that
+    # needs a product are folded in for free (one digit when qb is odd, two
+    # when even); three per remaining digit; the last step two, plus the
+    # top-left block when squarings follow; each squaring three, the last
+    # without the top-left block.
+    n = 1 + 3
+    top = (qb - 2) // 2
+    t = top - 1 if qb % 2 else (top - 2 if top > 0 else -1)
+    while t >= 0:
+        n += 3
+        t -= 1
+    n += 2 + (1 if s > 0 else 0)
     for j in range(s):
         n += 2 + (1 if j + 1 < s else 0)
     return n
@@ -31,7 +39,7 @@ def test_three_product_form_is_counted_where_used():
     f32 = bench.slice_flops(plan, d, 12, "fp32")
     f64 = bench.slice_flops(plan, d, 12, "fp64")
     b16 = bench.slice_flops(plan, d, 12, "bf16x3")
-    n_adj = 9 + 12
+    n_adj = 6 + 9
     assert f32["adjoint"] == 6.0 * d ** 3 * n_adj and f64["adjoint"] == 6.0 * d ** 3 * n_adj
     assert b16["adjoint"] == 24.0 * d ** 3 * n_adj and b16["adjoint_8d3"] == 8.0 * d ** 3 * n_adj
     # expm: q - 1 + s products; scans: one per direction; all three-product
