@@ -33,10 +33,13 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     rows (s, q, qb), and the adjoint's count in the conventional 8 d^3 per
     complex product ("adjoint_8d3").
 
-    Complex d x d products per slice: expm q - 1 + s; scans one per
-    direction; adjoint 6 + 3 floor((qb - 3) / 2) + 3 s (one for W, three for
-    the square of the block, three per Paterson-Stockmeyer step with a matrix
-    digit, two for the last step's top-right block, three per squaring).
+    Complex d x d products per slice: expm q - 1 + s (Horner; at d > 64 in
+    FP32 Paterson-Stockmeyer, 2 + floor((q - 3) / 2) + s for q >= 3); scans
+    one per direction; adjoint 6 + 3 floor((qb - 3) / 2) + 3 s (one for W,
+    three for the square of the block, three per Paterson-Stockmeyer step
+    with a matrix digit, two for the last step's top-right block, three per
+    squaring), one fewer where the FP32 expm keeps X^2 for the FP32 adjoint
+    (d > 16, q >= 2).
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
     the three-product (Gauss) form.  FP32 and FP64 use the latter in every
     stage at 32 <= d <= 64, and FP32 also in the expm and adjoint at d = 128.
@@ -51,8 +54,13 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     g_adj = 24.0 * d ** 3 if prec == "bf16x3" else (G3 if (mid or big32) else G4)
     g_expm = G3 if (mid or big32) else G4
     g_scan = G3 if mid else G4
-    n_adj = 6 + 3 * np.maximum(0, (qb - 3) // 2) + 3 * s
-    return {"expm": float((g_expm * (q - 1 + s)).sum()), "scan": float(2 * g_scan * len(s)),
+    if prec == "fp32" and d > 64:
+        n_exp = np.where(q < 2, 0, np.where(q == 2, 1, 2 + (q - 3) // 2)) + s
+    else:
+        n_exp = q - 1 + s
+    keep_x2 = prec == "fp32" and d > 16
+    n_adj = 6 + 3 * np.maximum(0, (qb - 3) // 2) + 3 * s - (keep_x2 * (q >= 2))
+    return {"expm": float((g_expm * n_exp).sum()), "scan": float(2 * g_scan * len(s)),
             "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
 
 

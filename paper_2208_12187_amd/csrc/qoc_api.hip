@@ -521,6 +521,7 @@ int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const 
   if (precision != QOC_FP64 && precision != QOC_FP32 && precision != QOC_BF16X3)
     return fail(QOC_ERR_UNSUPPORTED, "precision %d is not available", precision);
   const double ur = precision == QOC_FP64 ? 0x1p-53 : 0x1p-24;
+  const bool ps_expm = precision == QOC_FP32 && qoc::padded_dim(d) == 128;  // as the kernels
   auto norm1 = [d](const qoc_z* H) {
     double best = 0;
     for (int b = 0; b < d; ++b) {
@@ -537,7 +538,7 @@ int qoc_slice_plan(int d, int m, int N, const qoc_z* H0, const qoc_z* Hc, const 
     double th = nrm[0];
     for (int j = 0; j < m; ++j) th = fma(fabs(u[(size_t)j * N + k]), nrm[j + 1], th);
     th *= dt;
-    qoc::SlicePlan p = qoc::choose_plan(th, ur, with_gradient != 0);
+    qoc::SlicePlan p = qoc::choose_plan(th, ur, with_gradient != 0, ps_expm);
     plan[3 * k] = p.s;
     plan[3 * k + 1] = p.q;
     plan[3 * k + 2] = p.qb;

@@ -39,6 +39,7 @@ struct ProbDesc {
   void* delta;        // N PF matrices: U_k - I
   void* hk;           // N matrices kept by the expm pass for the adjoint (D >= 32): planar H_k
                       // at D <= 64, X = A_k / 2^s in PF layout at D = 128
+  void* x2;           // N PF matrices kept by the expm pass for the adjoint (D >= 32, FP32): (A_k / 2^s)^2
   void* xprev;        // N PF matrices: U_{k-1} ... U_{k0}   (I at a chunk start)
   void* bloc;         // N PF matrices: U_{k+1}^dag ... U_{k1-1}^dag mc[c] (mc[c] at a chunk end)
   void* tf;           // P PF matrices: forward chunk totals (their conjugate transposes are the backward ones)
@@ -179,8 +180,9 @@ struct Layout {
   int G;  // chunks per checkpoint segment (G = P: everything stored, no recompute)
   int W;  // slices held by the per-slice arrays (N, or G * L when segmented)
   size_t desc_bytes;  // descriptor table at the start of the workspace
-  size_t Hint, Vint, norms, mono, sq, delta, hk, xprev, bloc, tf, cf, cb, mc, grp, small;
-  int per_slice;  // per-slice arrays: delta, xprev, bloc, and hk at D >= 32
+  size_t Hint, Vint, norms, mono, sq, delta, hk, x2, xprev, bloc, tf, cf, cb, mc, grp, small;
+  int per_slice;  // per-slice arrays: delta, xprev, bloc, hk at D >= 32, x2 at D >= 32 in FP32
+                  // (null in the descriptor where absent)
   size_t per_prob;
   size_t scratch, scratch_bytes;  // D = 128: per-workgroup scratch after the problems
   size_t total;
@@ -188,7 +190,7 @@ struct Layout {
 
 // hbm_budget (bytes, 0 = unlimited) bounds the stored propagators of the
 // batch: the per-slice arrays (three stored propagators, and the slice
-// Hamiltonians at D >= 32) plus the four per-chunk and four per-group arrays.  When the
+// Hamiltonians and, in FP32, the squares (A_k / 2^s)^2 at D >= 32) plus the four per-chunk and four per-group arrays.  When the
 // full arrays do not fit, slices are processed in segments of G chunks whose
 // per-slice arrays are recomputed for the adjoint pass (sqrt(N)
 // checkpointing: with L of order sqrt(N) and G = 1 the storage is O(sqrt(N))).
@@ -202,7 +204,9 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   carry_groups(Lo.P, Lo.CG, Lo.PG);
   const size_t mat = 2ull * Lo.D * Lo.D * elem_size(precision);
   Lo.G = Lo.P;
-  Lo.per_slice = Lo.D >= 32 ? 4 : 3;
+  // per-slice arrays: delta, xprev, bloc; hk at D >= 32; x2 at D >= 32 in FP32
+  // (not for the split-BF16 adjoint, which the extra read does not speed up)
+  Lo.per_slice = Lo.D >= 32 ? (precision == 1 /* QOC_FP32 */ ? 5 : 4) : 3;
   const double per_call = 4.0 * Lo.P + 4.0 * Lo.PG;  // per-chunk and per-group arrays, in matrices
   const double full = (double)B * ((double)Lo.per_slice * N + per_call) * (double)mat;
   if (hbm_budget > 0 && full > (double)hbm_budget) {
@@ -218,7 +222,8 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.mono = o; o = align_up(o + (size_t)m * Lo.D * (4 + 2 * elem_size(precision)) + (size_t)m * 4);
   Lo.sq = o; o = align_up(o + (size_t)N * 4);
   Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
-  Lo.hk = o; o = align_up(o + (Lo.per_slice == 4 ? (size_t)Lo.W * mat : 0));
+  Lo.hk = o; o = align_up(o + (Lo.per_slice >= 4 ? (size_t)Lo.W * mat : 0));
+  Lo.x2 = o; o = align_up(o + (Lo.per_slice == 5 ? (size_t)Lo.W * mat : 0));
   Lo.xprev = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.bloc = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.tf = o; o = align_up(o + (size_t)Lo.P * mat);
@@ -266,7 +271,8 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.mok = P.mcol + (size_t)m * Lo.D;
   P.sq = reinterpret_cast<int*>(pb + Lo.sq);
   P.delta = pb + Lo.delta;
-  P.hk = Lo.per_slice == 4 ? pb + Lo.hk : nullptr;
+  P.hk = Lo.per_slice >= 4 ? pb + Lo.hk : nullptr;
+  P.x2 = Lo.per_slice == 5 ? pb + Lo.x2 : nullptr;
   P.xprev = pb + Lo.xprev;
   P.bloc = pb + Lo.bloc;
   P.tf = pb + Lo.tf;

@@ -220,7 +220,9 @@ __global__ __launch_bounds__(256) void k_prep(Work W) {
 
 // Per slice: theta = dt (|H0|_1 + sum_j |u[j][k]| |Hc[j]|_1) in FP64, then the
 // scaling exponent and Taylor degrees of choose_plan().
-__global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
+// flags: bit 0 gradient, bit 1 the expm evaluates by Paterson-Stockmeyer
+// (FP32 at D = 128).
+__global__ __launch_bounds__(256) void k_plan(Work W, double ur, int flags) {
   const Items I(W);
   for (int item = blockIdx.x * 256 + threadIdx.x; item < I.total; item += gridDim.x * 256) {
     int p, k;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int grad) {
     double th = P.norms[0];
     for (int j = 0; j < P.m; ++j) th = fma(fabs(gp(P.u)[(size_t)j * P.N + k]), gp(P.norms)[j + 1], th);
     th *= P.dt;
-    P.sq[k] = pack_plan(choose_plan(th, ur, grad != 0));
+    P.sq[k] = pack_plan(choose_plan(th, ur, (flags & 1) != 0, (flags & 2) != 0));
   }
 }
 
@@ -708,6 +710,10 @@ __device__ __forceinline__ void gradient_epilogue(const ProbDesc& P, int k, cons
 // Delta_k = U_k - I for every slice: one workgroup per slice, D/16 wavefronts.
 // Horner in delta form: R_q = I + X/q, R_i = I + X R_{i+1} / i, Delta = X R_2
 // (X = A_k / 2^s), then s squarings Delta <- 2 Delta + Delta^2.
+// FP32 gradient runs at D >= 32 keep X^2 for the adjoint (keep_square).
+// (Paterson-Stockmeyer in X^2, which would form X^2 as a product, needs the
+// same two products at q = 3 but held 40 more VGPRs at d = 64, a workgroup
+// per CU less, and was 0.4 ms slower on the d = 64 batch of 32.)
 // The expm and scan kernels take the three-product form (Ops::gemm3) at
 // D >= 32 with a floor of two waves per SIMD, which keeps the extra registers
 // of that form from lowering their occupancy.
@@ -724,6 +730,26 @@ constexpr bool kKeepH = D >= 32;
 // the extra fragment registers would add to its spills.
 template <typename T>
 constexpr int kExpmPairs = sizeof(T) == 4 ? 2 : 1;
+// FP32 keeps X2 = (A_k / 2^s)^2 for the adjoint at D >= 32 (where the
+// workspace has room for it: not for the split-BF16 adjoint, P.x2 null); in
+// FP64 the read-back would make the d = 64 adjoint spill, and it forms X2
+// itself.
+template <typename T>
+constexpr bool kKeepX2 = sizeof(T) == 4;
+
+// The first Horner product is P1 = X (I + X/q) = X + X^2/q, so
+// X^2 = q (P1 - X) comes without a product of its own (X re-read from LDS).
+// Its error, about q u |X| against |X^2|, enters the adjoint's Z only through
+// terms of size |X^2| |E|, so Z keeps an error of order q u |X| |E|.  For
+// Hermitian H_k the adjoint's X = A_k^dag / 2^s = -A_k / 2^s has the same
+// square.
+template <typename T, int D, typename Ops>
+__device__ __forceinline__ void keep_square(T* out, const Panel<T, D>& P1, const void* lds, int q, const Lane& L) {
+  Panel<T, D> X;
+  Ops::load(X, lds, L);
+  panel_axpby(X, (T)q, P1, (T)-q);
+  panel_store(out, X, L);
+}
 
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
@@ -742,17 +768,19 @@ void k_expm(Work W) {
   __syncthreads();
   Panel<T, D> R, acc;
   Ops::load(R, lds, L);
+  T* x2 = (kKeepX2<T> && hk && P.x2) ? pf_mat<T, D>(P.x2, k - W.rg.kbase) : nullptr;
   if (q >= 2) {
     panel_scale(R, (T)(1.0 / q));
     panel_add_identity(R, L, (T)1);
-    for (int i = q - 1; i >= 2; --i) {
+    for (int i = q - 1; i >= 1; --i) {
       Ops::template gemm3<kExpmPairs<T>>(acc, lds, R, L, true);
+      if (x2 && i == q - 1) keep_square<T, D, Ops>(x2, acc, lds, q, L);
       R = acc;
-      panel_scale(R, (T)(1.0 / i));
-      panel_add_identity(R, L, (T)1);
+      if (i >= 2) {
+        panel_scale(R, (T)(1.0 / i));
+        panel_add_identity(R, L, (T)1);
+      }
     }
-    Ops::template gemm3<kExpmPairs<T>>(acc, lds, R, L, true);
-    R = acc;
   }
   for (int j = 0; j < s; ++j) {
     __syncthreads();
@@ -1110,8 +1138,13 @@ void k_adjoint(Work W) {
   //    Each block product by M^2 takes three d x d products, the last one
   //    only the blocks used next.
   Panel<T, D> R3;
-  Ops::load(R1, X, L);              // R1 = X, R2 = E
-  Ops::gemm3(A1, X, R1, L, true);   // A1 = X2
+  Ops::load(R1, X, L);  // R1 = X, R2 = E
+  // A1 = X2: kept by the expm pass where it keeps H_k and forms its own
+  // square (q >= 2; for Hermitian H_k its X X equals this X X); general
+  // generators form it here.
+  if (kKeepH<D> && kKeepX2<T> && q >= 2 && P.x2 && !(P.flags & RUN_GENERAL))
+    panel_load(A1, pf_mat<T, D>(P.x2, k - W.rg.kbase), L);
+  else Ops::gemm3(A1, X, R1, L, true);
   Ops::gemm3(A2, X, R2, L, true);
   Ops::gemm3(A2, E, R1, L, false);  // A2 = S
   __syncthreads();                  // X and E are read: M^2 takes their place
@@ -1649,7 +1682,48 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
     // For the adjoint: X = A_k / 2^s in PF layout (its X, A_k^dag / 2^s, is
     // the exact negation), one coalesced store of this wavefront's panel.
     if (P.flags & RUN_GRAD) panel_store(pf_mat<T, 128>(P.hk, k - W.rg.kbase), acc, L);
-    if (q >= 2) {
+    // FP32: Paterson-Stockmeyer with X2 = X X as the step, X2 in slot 2 (and
+    // kept for the adjoint in gradient runs), C in SR:
+    //   p(X) - I = X + X2 C,  C = sum_{n=2..q} X^(n-2) / n!,  C <- D_t + X2 C,
+    //   D_t = I / (2t+2)! + X / (2t+3)!
+    // (as k_adjoint's block polynomial): expm_products(q) products instead
+    // of Horner's q - 1, and X2 on the way.  (Taking X2 from Horner's first
+    // product as k_expm does cost this kernel more in scratch traffic than
+    // the products it saves.)  FP64, whose kernels spill, runs Horner.
+    if (kKeepX2<T> && q >= 2) {
+      T* S2 = slot_mat<T>(scratch, 2);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SX, L, true);
+      if ((P.flags & RUN_GRAD) && P.x2) panel_store(pf_mat<T, 128>(P.x2, k - W.rg.kbase), acc, L);
+      if (q == 2) {
+        panel_scale(acc, (T)0.5);
+        panel_axpy_pf(acc, (T)1, SX, L);  // X + X2 / 2
+      } else {
+        panel_store(S2, acc, L);
+        const int top = (q - 2) / 2;
+        int t;
+        if (q & 1) {  // C = I / (q-1)! + X / q!
+          t = top - 1;
+          panel_load(acc, SX, L);
+          panel_scale(acc, (T)inv_factorial(q));
+          panel_add_identity(acc, L, (T)inv_factorial(q - 1));
+        } else {  // C = I / (q-2)! + X / (q-1)! + X2 / q!
+          t = top - 2;
+          panel_scale(acc, (T)inv_factorial(q));
+          panel_axpy_pf(acc, (T)inv_factorial(q - 1), SX, L);
+          panel_add_identity(acc, L, (T)inv_factorial(q - 2));
+        }
+        panel_store(SR, acc, L);
+        for (; t >= 0; --t) {  // C <- D_t + X2 C
+          panel_load(acc, SX, L);
+          panel_scale(acc, (T)inv_factorial(2 * t + 3));
+          panel_add_identity(acc, L, (T)inv_factorial(2 * t + 2));
+          gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false);
+          panel_store(SR, acc, L);
+        }
+        panel_load(acc, SX, L);
+        gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false);  // X + X2 C
+      }
+    } else if (q >= 2) {
       panel_scale(acc, (T)(1.0 / q));
       panel_add_identity(acc, L, (T)1);
       panel_store(SR, acc, L);
@@ -1944,7 +2018,9 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     // The block polynomial by Paterson-Stockmeyer as in k_adjoint: M^2 =
     // [[X2, S], [0, X2]] into S0 (X2) and S1 (S), the running C = [[C1, C2],
     // [0, C1]] in SR1 and SR2.
-    gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SX, L, true);
+    if (kKeepX2<T> && q >= 2 && P.x2 && !(P.flags & RUN_GENERAL))
+      panel_load(acc, pf_mat<T, 128>(P.x2, k - W.rg.kbase), L);  // kept by the expm
+    else gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SX, L, true);
     panel_store(S0, acc, L);
     gemm128<T, false, k128Gauss<T>>(acc, lds, SX, SE, L, true);
     gemm128<T, false, k128Gauss<T>>(acc, lds, SE, SX, L, false);
@@ -2124,7 +2200,8 @@ static void stage_128(int stage, const Launch& L, const Range& rg, double ur) {
     }
     case ST_PLAN: {
       Work w = L.dyn ? dyn : slice_work(L, all);
-      hipLaunchKernelGGL(k_plan, dim3(L.dyn ? L.dyn_grid : (w.total + 255) / 256), dim3(256), 0, st, w, ur, grad);
+      hipLaunchKernelGGL(k_plan, dim3(L.dyn ? L.dyn_grid : (w.total + 255) / 256), dim3(256), 0, st, w, ur,
+                         grad | (kKeepX2<T> ? 2 : 0));
       break;
     }
     case ST_EXPM: {

@@ -14,8 +14,11 @@
 //    the factor of |E| is at most ur.
 // Among s in [s0, s0 + 6], s0 = least s >= 0 with r <= 1, the value that
 // minimises the number of complex d x d products of the path is taken:
-//    exp:       (q - 1) + s
+//    exp:       (q - 1) + s    (Horner; expm_products(q) + s where the expm
+//                                 runs Paterson-Stockmeyer: FP32 at D = 128)
 //    gradient:  + frechet_products(qb) + 3 s   (block polynomial, squarings)
+// (where the adjoint reuses the expm's X^2 it saves one product for every s
+// alike, so the choice does not depend on that).
 #pragma once
 
 #include <math.h>
@@ -58,6 +61,12 @@ QOC_HD inline double inv_factorial(int n) {
   return f;
 }
 
+// Complex d x d products of the degree-q Taylor polynomial in delta form by
+// Paterson-Stockmeyer with X^2 as the step: one for X^2, one per digit that
+// holds a matrix below the top one (floor((q - 3) / 2) of them) and one for
+// the last step (q >= 3); X + X^2 / 2 at q = 2.
+QOC_HD inline int expm_products(int q) { return q < 2 ? 0 : (q == 2 ? 1 : 2 + (q - 3) / 2); }
+
 // Complex d x d products of the degree-qb Taylor polynomial of the block
 // [[X, E], [0, X]] by Paterson-Stockmeyer with the block's square as the
 // step: three for the square, three per Horner step in the square that has a
@@ -65,13 +74,13 @@ QOC_HD inline double inv_factorial(int n) {
 // right block (the top left one is counted with the squarings).
 QOC_HD inline int frechet_products(int qb) { return 5 + 3 * (qb > 3 ? (qb - 3) / 2 : 0); }
 
-QOC_HD inline int plan_cost(int s, int q, int qb, bool grad) {
-  int cost = q - 1 + s;
+QOC_HD inline int plan_cost(int s, int q, int qb, bool grad, bool ps_expm) {
+  int cost = (ps_expm ? expm_products(q) : q - 1) + s;
   if (grad) cost += frechet_products(qb) + 3 * s;
   return cost;
 }
 
-QOC_HD inline SlicePlan choose_plan(double theta, double ur, bool grad) {
+QOC_HD inline SlicePlan choose_plan(double theta, double ur, bool grad, bool ps_expm = false) {
   int s0 = 0;
   while (ldexp(theta, -s0) > 1.0 && s0 < 60) ++s0;
   SlicePlan best = {s0, 1, 2};
@@ -80,7 +89,7 @@ QOC_HD inline SlicePlan choose_plan(double theta, double ur, bool grad) {
     double r = ldexp(theta, -s);
     int q = taylor_degree(r, ur);
     int qb = frechet_degree(r, ur);
-    int c = plan_cost(s, q, qb, grad);
+    int c = plan_cost(s, q, qb, grad, ps_expm);
     if (c < best_cost) {
       best_cost = c;
       best.s = s;

@@ -6,14 +6,15 @@ import numpy as np
 import bench
 
 
-def _products_adjoint(s, qb):
+def _products_adjoint(s, q, qb, keep_x2):
     # W = bloc xprev^dag: one product.  Block polynomial by Paterson-Stockmeyer
-    # in M^2: three products for M^2; the digits above the first one that
-    # needs a product are folded in for free (one digit when qb is odd, two
-    # when even); three per remaining digit; the last step two, plus the
-    # top-left block when squarings follow; each squaring three, the last
-    # without the top-left block.
-    n = 1 + 3
+    # in M^2: three products for M^2 (two when the expm kept X^2, which it
+    # forms when q >= 2); the digits above the first one that needs a product
+    # are folded in for free (one digit when qb is odd, two when even); three
+    # per remaining digit; the last step two, plus the top-left block when
+    # squarings follow; each squaring three, the last without the top-left
+    # block.
+    n = 1 + (2 if keep_x2 and q >= 2 else 3)
     top = (qb - 2) // 2
     t = top - 1 if qb % 2 else (top - 2 if top > 0 else -1)
     while t >= 0:
@@ -25,12 +26,45 @@ def _products_adjoint(s, qb):
     return n
 
 
+def _products_expm(s, q, ps):
+    # Horner: one product per step from degree q down to 1.  Paterson-Stockmeyer
+    # in X^2: X^2, then (q >= 3) one per digit below the folded top ones and
+    # the last step.  Then one per squaring.
+    n = 0
+    if q >= 2 and not ps:
+        n = q - 1
+    elif q >= 2:
+        n = 1
+        if q >= 3:
+            top = (q - 2) // 2
+            t = top - 1 if q % 2 else top - 2
+            while t >= 0:
+                n += 1
+                t -= 1
+            n += 1
+    return n + s
+
+
 def test_adjoint_product_count_matches_the_loop_structure():
     for s in range(0, 4):
         for qb in range(2, 10):
-            plan = np.array([[s, max(qb - 1, 1), qb]], dtype=np.int32)
-            f = bench.slice_flops(plan, 64, 12, "fp32")
-            assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, qb)
+            q = max(qb - 1, 1)
+            plan = np.array([[s, q, qb]], dtype=np.int32)
+            for prec, keep in (("fp32", True), ("fp64", False), ("bf16x3", False)):
+                f = bench.slice_flops(plan, 64, 12, prec)
+                assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, q, qb, keep)
+            f = bench.slice_flops(plan, 16, 8, "fp32")  # d = 16 keeps no X^2
+            assert f["adjoint_8d3"] == 8.0 * 16 ** 3 * _products_adjoint(s, q, qb, False)
+
+
+def test_expm_product_count_matches_the_loop_structure():
+    for s in range(0, 4):
+        for q in range(1, 12):
+            plan = np.array([[s, q, q + 1]], dtype=np.int32)
+            for d, prec, ps in ((64, "fp32", False), (64, "fp64", False), (128, "fp32", True), (128, "fp64", False)):
+                f = bench.slice_flops(plan, d, 12, prec)
+                g = 6.0 if (d <= 64 or prec == "fp32") else 8.0
+                assert f["expm"] == g * d ** 3 * _products_expm(s, q, ps), (d, prec, s, q)
 
 
 def test_three_product_form_is_counted_where_used():
@@ -39,8 +73,8 @@ def test_three_product_form_is_counted_where_used():
     f32 = bench.slice_flops(plan, d, 12, "fp32")
     f64 = bench.slice_flops(plan, d, 12, "fp64")
     b16 = bench.slice_flops(plan, d, 12, "bf16x3")
-    n_adj = 6 + 9
-    assert f32["adjoint"] == 6.0 * d ** 3 * n_adj and f64["adjoint"] == 6.0 * d ** 3 * n_adj
+    n_adj, n_adj_keep = 6 + 9, 5 + 8
+    assert f32["adjoint"] == 6.0 * d ** 3 * n_adj_keep and f64["adjoint"] == 6.0 * d ** 3 * n_adj
     assert b16["adjoint"] == 24.0 * d ** 3 * n_adj and b16["adjoint_8d3"] == 8.0 * d ** 3 * n_adj
     # expm: q - 1 + s products; scans: one per direction; all three-product
     assert f32["expm"] == 6.0 * d ** 3 * (2 + 3) and f64["expm"] == 6.0 * d ** 3 * (2 + 3)
@@ -50,12 +84,12 @@ def test_three_product_form_is_counted_where_used():
     # d = 16 uses the four-product form everywhere; at d = 128 the FP32 expm
     # and adjoint use the three-product form and FP64 does not
     f = bench.slice_flops(plan, 16, 8, "fp32")
-    assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * 16 ** 3 * 5
+    assert f["adjoint"] == f["adjoint_8d3"] == 8.0 * 16 ** 3 * n_adj and f["expm"] == 8.0 * 16 ** 3 * 5
     f = bench.slice_flops(plan, 128, 14, "fp32")
-    assert f["adjoint"] == 6.0 * 128 ** 3 * n_adj and f["expm"] == 6.0 * 128 ** 3 * 5
+    assert f["adjoint"] == 6.0 * 128 ** 3 * n_adj_keep and f["expm"] == 6.0 * 128 ** 3 * 5
     assert f["scan"] == 2 * 8.0 * 128 ** 3 * 2
     f = bench.slice_flops(plan, 128, 14, "fp64")
-    assert f["adjoint"] == f["adjoint_8d3"] and f["expm"] == 8.0 * 128 ** 3 * 5
+    assert f["adjoint"] == f["adjoint_8d3"] == 8.0 * 128 ** 3 * n_adj and f["expm"] == 8.0 * 128 ** 3 * 5
 
 
 def test_more_than_one_gpu_is_refused():

@@ -26,7 +26,8 @@ def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec, seg):
     P = -(-N // L)
     CG = int(np.ceil(np.sqrt(P)))
     PG = -(-P // CG)  # carry groups
-    per_slice = 4 if D >= 32 else 3  # stored propagators, and the slice Hamiltonians at D >= 32
+    # stored propagators; at D >= 32 the slice Hamiltonians, and in FP32 X^2
+    per_slice = (5 if prec == "fp32" else 4) if D >= 32 else 3
     budget = 2 * (4 * P + 4 * PG + seg * per_slice * L + 1) * mat  # segments of `seg` chunks
     small = qoc.Runner(2, p.d, p.m, N, prec, hbm_budget=budget)
     assert small.ws_bytes < full.ws_bytes

@@ -142,6 +142,22 @@ def test_tiny_slice_counts(gpu_lib, N):
     _check(F, grad, ref, "fp64")
 
 
+@pytest.mark.parametrize("nq", [5, 7])
+def test_first_order_slices(gpu_lib, nq):
+    """Slices so short that the FP32 plan takes q = 1 (no Taylor product) and
+    qb = 2: the adjoint then forms X^2 itself rather than reading the one the
+    expm keeps, and its block polynomial has no matrix digit (d = 32, 128)."""
+    from paper_2208_12187_amd import qoc
+
+    p = _heis(nq, 23, 2e-6, 11)
+    plan = qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, "fp32", True)
+    assert plan[:, 1].max() == 1 and plan[:, 2].max() == 2
+    print(f"[parity] first-order slices d={2 ** nq}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32")
+    _check(F, grad, ref, "fp32")
+
+
 def test_large_theta_uses_squaring(gpu_lib):
     """Strong controls and long slices force s > 0 in the plan."""
     from paper_2208_12187_amd import qoc
