@@ -73,8 +73,9 @@ typedef struct {
                              the host and ignore it: a non-Hermitian or non-finite
                              input gives unspecified results there, never an error. */
   uint64_t hbm_budget;    /* bytes for the per-slice and per-chunk arrays of a call
-                             (stored propagators, and the slice Hamiltonians
-                             at d > 16); 0 = no limit.
+                             (stored propagators, and at d > 16 the slice
+                             Hamiltonians and, in QOC_FP32, the squares
+                             (A_k / 2^s)^2 kept for the adjoint); 0 = no limit.
                              When those arrays exceed it, slices are
                              processed in checkpoint segments and recomputed
                              for the gradient pass (same results, more work).
@@ -283,8 +284,9 @@ const char* qoc_stage_name(int stage);
  * Requests are queued by qoc_engine_submit (host inputs are copied into the
  * engine's pinned staging before it returns) and admitted in FIFO order
  * while their device footprint (qoc_engine_footprint: inputs, outputs and
- * the per-slice arrays of the path, about 4 N D^2 c bytes at D >= 32 and
- * 3 N D^2 c at D = 16, with c the bytes of one complex element) fits the
+ * the per-slice arrays of the path, about 5 N D^2 c bytes at D >= 32 in
+ * QOC_FP32, 4 N D^2 c in the other precisions and 3 N D^2 c at D = 16, with
+ * c the bytes of one complex element) fits the
  * engine's device pool and one of max_active descriptor slots is free.
  * Admitted requests are grouped by padded dimension D (16, 32, 64, 128); each
  * group has its own stream and a captured graph of the path's kernels that a
