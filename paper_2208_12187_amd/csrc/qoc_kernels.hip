@@ -880,13 +880,20 @@ __device__ __forceinline__ void reunitarise(const ProbDesc& P, Panel<float, D>& 
 // bloc[k] = S before slice k is applied, so that the adjoint's
 // W_k = bloc[k] xprev[k]^dag takes one product.  (The backward chunk total
 // that the carry needs is tf[c]^dag.)  Each step is S <- S + Delta S (or
-// Delta^dag S) with Delta staged in LDS, double-buffered.
+// Delta^dag S) with Delta staged in LDS (the next Delta is loaded into
+// registers during a step).  The LDS buffer is double (no barrier before it
+// is refilled) except in FP32 at D = 64, where one buffer and a barrier let
+// three workgroups share a CU instead of two (measured on the d = 64 batch
+// of 32: backward scans 1.00 -> 0.94 ms; FP64, held to one workgroup per CU
+// by its registers, lost a third with one buffer).
+template <typename T, int D>
+constexpr int kScanBufs = (sizeof(T) == 4 && D == 64) ? 1 : 2;
+
 template <typename T, int D, typename Ops, bool PERSIST>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
 void k_scan_local(Work W, int dir) {
-  __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
+  __shared__ __align__(16) unsigned char lds[kScanBufs<T, D>][Ops::BYTES];
   const int bwd = dir < 0 ? (int)blockIdx.y : dir;  // dir < 0: both passes, one per blockIdx.y
-  __shared__ double red[D / 16];
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -901,7 +908,8 @@ void k_scan_local(Work W, int dir) {
   int k = bwd ? k1 - 1 : k0;
   panel_load(nxt, pf_mat<T, D>(P.delta, k - W.rg.kbase), L);
   for (int i = 0; i < n; ++i) {
-    void* buf = lds[i & 1];
+    void* buf = lds[i % kScanBufs<T, D>];
+    if (kScanBufs<T, D> == 1 && i > 0) __syncthreads();  // every wavefront is done with the previous factor
     if (bwd) Ops::store_ct(buf, nxt, L); else Ops::store(buf, nxt, L);
     const int kn = bwd ? k - 1 : k + 1;
     // the store of S before the prefetch of the next Delta, so that the wait
@@ -913,15 +921,35 @@ void k_scan_local(Work W, int dir) {
     panel_axpby(S, (T)1, acc, (T)1);
     k = kn;
   }
-  if (!bwd && !W.rg.recompute) {
-    if constexpr (sizeof(T) == 4) {
-      static_assert(2 * Ops::BYTES >= (int)sizeof(double) * Mat<double, D>::LDS_ELEMS, "LDS too small");
-      if (P.reun_tol >= 0) reunitarise<D>(P, S, &lds[0][0], red, L);
-    }
-    panel_store(pf_mat<T, D>(P.tf, c), S, L);
-  }
+  if (!bwd && !W.rg.recompute) panel_store(pf_mat<T, D>(P.tf, c), S, L);  // (k_reun follows in FP32)
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
+  }
+}
+
+// The re-unitarisation of the forward chunk totals tf[c] (FP32, problems with
+// reun_tol >= 0), after the forward scans: one workgroup per chunk runs
+// reunitarise() on the stored total.  A kernel of its own, so that the scan
+// keeps the registers and LDS of its chain alone: inside it, the check's
+// FP64 registers and its FP64 matrix in LDS cost the scan a workgroup per CU.
+template <int D, bool PERSIST>
+__global__ __launch_bounds__(4 * D) void k_reun(Work W) {
+  __shared__ __align__(16) double lds[Mat<double, D>::LDS_ELEMS];
+  __shared__ double red[D / 16];
+  Lane L;
+  const Items I(W);
+  for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
+    int p, c;
+    split_item(item, W.rg.c_lo, W.rg.c_n, I.start, I.nprob, p, c);
+    const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
+    if (P.reun_tol >= 0) {  // uniform over the workgroup
+      Panel<float, D> S;
+      panel_load(S, pf_mat<float, D>(P.tf, c), L);
+      reunitarise<D>(P, S, lds, red, L);
+      panel_store(pf_mat<float, D>(P.tf, c), S, L);
+    }
+    if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
+    __syncthreads();
   }
 }
 
@@ -2157,6 +2185,12 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
       const dim3 grid(grid_of(L, w.total, 0), both ? 2 : 1);
       if (L.dyn) hipLaunchKernelGGL((k_scan_local<T, D, Ops, true>), grid, dim3(NT), 0, st, w, dir);
       else hipLaunchKernelGGL((k_scan_local<T, D, Ops, false>), grid, dim3(NT), 0, st, w, dir);
+      if constexpr (sizeof(T) == 4) {
+        if (stage == ST_SCAN && !rg.recompute) {
+          if (L.dyn) hipLaunchKernelGGL((k_reun<D, true>), dim3(grid.x), dim3(NT), 0, st, w);
+          else hipLaunchKernelGGL((k_reun<D, false>), dim3(grid.x), dim3(NT), 0, st, w);
+        }
+      }
       }
       break;
     }
