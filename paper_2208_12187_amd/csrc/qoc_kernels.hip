@@ -1327,13 +1327,17 @@ __device__ __forceinline__ void stage128(T* lds, const T* M, int h, const Lane& 
 }
 
 // acc (+)= M B, M (or M^dag when CT) staged through LDS part by part, B this
-// wavefront's panel of a PF matrix.  Starts and ends every part with a
-// workgroup barrier, so M may have been written by any wavefront.  G3 selects
-// the three-product form of the complex product (as cgemm3m: T1 in acc.re,
-// T3 in acc.im starting at acc.im + acc.re, T2 apart).
+// wavefront's panel of a PF matrix.  Every part is staged between two
+// workgroup barriers, so M may have been written by any wavefront.  With
+// stage = false and the whole matrix in one part (FP32), M is taken to be in
+// LDS already from the previous product, which had the same left factor and
+// no LDS writes since: one barrier (which also completes this wavefront's
+// stores of B) and no staging.  G3 selects the three-product form of the
+// complex product (as cgemm3m: T1 in acc.re, T3 in acc.im starting at
+// acc.im + acc.re, T2 apart).
 template <typename T, bool CT, bool G3 = false>
 __device__ __forceinline__ void gemm128(Panel<T, 128>& acc, T* lds, const T* M, const T* B, const Lane& L,
-                                        bool zero_acc) {
+                                        bool zero_acc, bool stage = true) {
   using K = K128<T>;
   using v4 = typename Prec<T>::v4;
   const T* lim = lds + K::D * K::SD;
@@ -1350,8 +1354,10 @@ __device__ __forceinline__ void gemm128(Panel<T, 128>& acc, T* lds, const T* M, 
 #pragma unroll
   for (int h = 0; h < K::HALVES; ++h) {
     __syncthreads();
-    stage128<T, CT>(lds, M, h, L);
-    __syncthreads();
+    if (stage || K::HALVES > 1) {
+      stage128<T, CT>(lds, M, h, L);
+      __syncthreads();
+    }
     constexpr int STEPS = K::KBH * K::RB;
     v4 ar[2], ai[2], br[2], bi[2];
     ar[0] = Prec<T>::ld4(lds + base);
@@ -1741,15 +1747,17 @@ __global__ __launch_bounds__(512) void k_expm128(Work W, void* scratch) {
           panel_add_identity(acc, L, (T)inv_factorial(q - 2));
         }
         panel_store(SR, acc, L);
+        bool staged = false;  // X2 already in LDS (from the previous product)
         for (; t >= 0; --t) {  // C <- D_t + X2 C
           panel_load(acc, SX, L);
           panel_scale(acc, (T)inv_factorial(2 * t + 3));
           panel_add_identity(acc, L, (T)inv_factorial(2 * t + 2));
-          gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false);
+          gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false, !staged);
+          staged = true;
           panel_store(SR, acc, L);
         }
         panel_load(acc, SX, L);
-        gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false);  // X + X2 C
+        gemm128<T, false, k128Gauss<T>>(acc, lds, S2, SR, L, false, !staged);  // X + X2 C
       }
     } else if (q >= 2) {
       panel_scale(acc, (T)(1.0 / q));
@@ -2082,23 +2090,27 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
       panel_add_identity(acc, L, (T)0.5);
       panel_store(SR1, acc, L);
     }
+    // Products with X2 as the left factor follow each other where they can
+    // (S C1 first in a step), so that X2 stays in LDS between them (FP32).
+    bool x2_staged = false;
     for (; t >= 0; --t) {  // C <- D_t + M^2 C (own panels of SR1, SR2 only)
       const T a = (T)inv_factorial(2 * t + 2), b = (T)inv_factorial(2 * t + 3);
       panel_load(acc, SE, L);
       panel_scale(acc, b);
-      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false);
       gemm128<T, false, k128Gauss<T>>(acc, lds, S1, SR1, L, false);
-      panel_store(SR2, acc, L);  // b E + X2 C2 + S C1
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false);
+      panel_store(SR2, acc, L);  // b E + S C1 + X2 C2
       panel_load(acc, SX, L);
       panel_scale(acc, b);
       panel_add_identity(acc, L, a);
-      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR1, L, false);
+      gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR1, L, false, false);
       panel_store(SR1, acc, L);  // a I + b X + X2 C1
+      x2_staged = true;
     }
     // Q = E + X2 C2 + S C1 and, when squaring follows, D1 = X + X2 C1 (into
     // S1 once every wavefront has staged S; Q waits in the own panel of SE).
     panel_load(acc, SE, L);
-    gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false);
+    gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR2, L, false, !x2_staged);
     gemm128<T, false, k128Gauss<T>>(acc, lds, S1, SR1, L, false);
     if (s > 0) {
       panel_store(SE, acc, L);

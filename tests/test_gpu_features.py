@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("cfg,N,prec,seg", [(3, 300, "fp32", 1), (3, 300, "fp32", 2), (4, 60, "fp64", 1),
-                                            (2, 101, "fp64", 1)])
+                                            (4, 60, "fp32", 1), (2, 101, "fp64", 1)])
 def test_checkpointing_is_bitwise_identical(gpu_lib, cfg, N, prec, seg):
     import torch
     from paper_2208_12187_amd import qoc
