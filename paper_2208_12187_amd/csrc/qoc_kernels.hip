@@ -751,8 +751,15 @@ __device__ __forceinline__ void keep_square(T* out, const Panel<T, D>& P1, const
   panel_store(out, X, L);
 }
 
+// The FP32 d = 64 expm (one slice per workgroup) takes a floor of four waves
+// per SIMD: it needs 130 VGPRs otherwise, and at 128 (two spilled) four
+// workgroups share a CU instead of three (expm 1.88 -> 1.80 ms on the d = 64
+// batch of 32).  The engine's persistent instance keeps the floor of two.
+template <typename T, int D, bool PERSIST>
+constexpr int kExpmWaves = (sizeof(T) == 4 && D == 64 && !PERSIST) ? 4 : kMinWaves<D>;
+
 template <typename T, int D, typename Ops, bool PERSIST>
-__global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kMinWaves<D>)))
+__global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kExpmWaves<T, D, PERSIST>)))
 void k_expm(Work W) {
   __shared__ __align__(16) unsigned char lds[Ops::BYTES];
   Lane L;
