@@ -28,7 +28,30 @@ CFG = 3  # 6-qubit Ising chain, d = 64
 WORKLOADS = {2: "4-qubit Heisenberg chain", 3: "6-qubit Ising chain", 4: "7-qubit Heisenberg chain"}
 
 
-def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
+def permutation_runs(Hc: np.ndarray, group: int = 4):
+    """For controls with one nonzero per row whose columns form a permutation
+    (Pauli strings), the number of dot-product sets the FP32 adjoint's sampled
+    last step forms per column: controls in one group of `group` with the
+    previous control's columns share one.  None when some control is not such
+    a permutation (the adjoint then takes its last two products)."""
+    d = Hc.shape[1]
+    cols = []
+    for H in Hc:
+        nz = H != 0
+        if (nz.sum(axis=1) > 1).any():
+            return None
+        col = np.where(nz.any(axis=1), nz.argmax(axis=1), np.arange(d))
+        if len(set(col.tolist())) != d:
+            return None
+        cols.append(col)
+    runs = 0
+    for j in range(len(cols)):
+        if j % group == 0 or not np.array_equal(cols[j], cols[j - 1]):
+            runs += 1
+    return runs
+
+
+def slice_flops(plan: np.ndarray, d: int, m: int, prec: str, runs=None) -> dict:
     """MFMA flops per stage of the implemented algorithm for slices with plan
     rows (s, q, qb), and the adjoint's count in the conventional 8 d^3 per
     complex product ("adjoint_8d3").
@@ -39,7 +62,9 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
     three for the square of the block, three per Paterson-Stockmeyer step
     with a matrix digit, two for the last step's top-right block, three per
     squaring), one fewer where the FP32 expm keeps X^2 for the FP32 adjoint
-    (d > 16, q >= 2).
+    (d > 16, q >= 2), and two fewer where the FP32 adjoint samples its last step
+    (16 < d <= 64, s = 0, `runs` not None: permutation controls), which costs
+    16 d^2 runs real flops on the vector ALU instead ("adjoint_valu").
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
     the three-product (Gauss) form.  FP32 and FP64 use the latter in every
     stage at 32 <= d <= 64, and FP32 also in the expm and adjoint at d = 128.
@@ -60,8 +85,12 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str) -> dict:
         n_exp = q - 1 + s
     keep_x2 = prec == "fp32" and d > 16
     n_adj = 6 + 3 * np.maximum(0, (qb - 3) // 2) + 3 * s - (keep_x2 * (q >= 2))
+    sampled = (s == 0) if (prec == "fp32" and 16 < d <= 64 and runs is not None) else np.zeros_like(s, dtype=bool)
+    n_adj = n_adj - 2 * sampled
+    valu = float((16.0 * d * d * (runs or 0) * sampled).sum())
     return {"expm": float((g_expm * n_exp).sum()), "scan": float(2 * g_scan * len(s)),
-            "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum())}
+            "adjoint": float((g_adj * n_adj).sum()), "adjoint_8d3": float((8.0 * d ** 3 * n_adj).sum()),
+            "adjoint_valu": valu}
 
 
 def worst_rel_grad_err(grad, ref):
@@ -355,7 +384,10 @@ def main():
     batch = qoc.Batch.from_problems(problems)
     plans = {pr: np.concatenate([qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, pr, True) for p in problems])
              for pr in ("fp32", "fp64", "bf16x3")}
-    flops = {pr: slice_flops(plans[pr], d, m, pr) for pr in plans}
+    runs = permutation_runs(problems[0].Hc)
+    flops = {pr: slice_flops(plans[pr], d, m, pr, runs) for pr in plans}
+    # the dense control kernels take every product (no sampled last step)
+    flops_dense = slice_flops(plans.get(args.precision, plans["fp32"]), d, m, args.precision)
 
     def leg(prec, steps, bsz=B, bat=batch, dense_controls=False):
         r = qoc.Runner(bsz, d, m, N, prec, dense_controls=dense_controls)
@@ -383,10 +415,11 @@ def main():
                  "dispatch, each scaled by its reading for a plain 1 GiB copy), used because its kernel-source "
                  "hash matches this build; not measured in this run"),
                 "kernel": "k_adjoint", "avg_launch_ms": round(adj_ms / max(adj_n, 1), 4),
-                "cgemm_8d3_tflops": round(flops[args.precision]["adjoint_8d3"] / adj_avg_s / 1e12, 2)}
+                "cgemm_8d3_tflops": round(flops[args.precision]["adjoint_8d3"] / adj_avg_s / 1e12, 2),
+                "sampled_valu_tflops": round(flops[args.precision]["adjoint_valu"] / adj_avg_s / 1e12, 2)}
 
     def path_flops(pr):
-        return sum(v for k, v in flops[pr].items() if k != "adjoint_8d3")
+        return sum(v for k, v in flops[pr].items() if k not in ("adjoint_8d3", "adjoint_valu"))
 
     total_flops = path_flops(args.precision)
     stages = {k: round(v[0] / max(v[1], 1), 4) for k, v in head["stages"].items() if v[1]}
@@ -401,7 +434,8 @@ def main():
                                    "ms_per_step": round(dn["ms_per_step"], 3),
                                    "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in dn["stages"].items()
                                                  if v[1]},
-                                   "adjoint_frac": round(adj_flops / (adn_ms / max(adn_n, 1) / 1e3) / 1e12 / peak, 4),
+                                   "adjoint_frac": round(flops_dense["adjoint"] / (adn_ms / max(adn_n, 1) / 1e3) / 1e12
+                                                         / peak, 4),
                                    "max_abs_dF": float(np.max(np.abs(dn["F"] - head["F"]))),
                                    "grad_err_rel": worst_rel_grad_err(dn["grad"], head["grad"])}
     if not args.no_fp64 and args.precision != "fp64":

@@ -34,7 +34,11 @@ struct ProbDesc {
   double* norms;      // m+1 one-norms of H0, Hc[j] (FP64)
   int* mcol;          // m*D: column of the nonzero of row a of Hc[j] (a if the row is empty)
   void* mval;         // m*D complex values (re, im) of those entries, in precision T
-  int* mok;           // m flags: Hc[j] has at most one nonzero per row (and D <= 64)
+  int* mok;           // m flags: bit 0, Hc[j] has at most one nonzero per row (dense kernels not
+                      // forced); bit 1, also a bijection from rows to columns (a permutation
+                      // with weights: Pauli strings)
+  int* minv;          // m*D: row a with col_j(a) = b, valid where mok bit 1 is set (null where
+                      // no layout holds it)
   int* sq;            // per slice: s | q << 8 | qb << 16
   void* delta;        // N PF matrices: U_k - I
   void* hk;           // N matrices kept by the expm pass for the adjoint (D >= 32): planar H_k
@@ -219,7 +223,7 @@ inline Layout make_layout(int B, int d, int m, int N, int precision, int chunk, 
   Lo.Hint = o; o = align_up(o + (size_t)(m + 1) * mat);
   Lo.Vint = o; o = align_up(o + mat);
   Lo.norms = o; o = align_up(o + (size_t)(m + 1) * 8);
-  Lo.mono = o; o = align_up(o + (size_t)m * Lo.D * (4 + 2 * elem_size(precision)) + (size_t)m * 4);
+  Lo.mono = o; o = align_up(o + (size_t)m * Lo.D * (8 + 2 * elem_size(precision)) + (size_t)m * 4);
   Lo.sq = o; o = align_up(o + (size_t)N * 4);
   Lo.delta = o; o = align_up(o + (size_t)Lo.W * mat);
   Lo.hk = o; o = align_up(o + (Lo.per_slice >= 4 ? (size_t)Lo.W * mat : 0));
@@ -269,6 +273,7 @@ inline void fill_desc(ProbDesc& P, const Layout& Lo, char* pb, int d, int m, int
   P.mval = pb + Lo.mono;
   P.mcol = reinterpret_cast<int*>(pb + Lo.mono + (size_t)m * Lo.D * 2 * Lo.esize);
   P.mok = P.mcol + (size_t)m * Lo.D;
+  P.minv = P.mok + m;
   P.sq = reinterpret_cast<int*>(pb + Lo.sq);
   P.delta = pb + Lo.delta;
   P.hk = Lo.per_slice >= 4 ? pb + Lo.hk : nullptr;

@@ -90,10 +90,13 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
   const int d = P.d;
   const int a = threadIdx.x;
   const bool gen = (P.flags & RUN_GENERAL) != 0;  // stored as i G (see prep_one)
-  int multi = 0;
+  __shared__ int hits[D];  // rows whose entry lies in each column
+  if (a < D) hits[a] = 0;
+  __syncthreads();
+  int multi = 0, col = a;
   {
     if (a < D) {
-      int col = a, cnt = 0;
+      int cnt = 0;
       T vr = 0, vi = 0;
       if (a < d)
         for (int c = 0; c < d; ++c) {
@@ -111,10 +114,28 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
       gp(P.mcol)[idx] = col;
       gp(reinterpret_cast<T*>(P.mval))[2 * idx] = vr;
       gp(reinterpret_cast<T*>(P.mval))[2 * idx + 1] = vi;
+      atomicAdd(&hits[col], 1);
     }
   }
+  // Whether control j - 1 puts its entries at the same columns (X_i and Y_i
+  // do), from its source rows: then the entries of Z that both read are the
+  // same (flag 4).
+  int same = 1;
+  if (j > 0 && a < d) {
+    const double* prev = src - 2 * (size_t)d * d;
+    int pc = a;
+    for (int c = 0; c < d; ++c)
+      if (prev[2 * (a * d + c)] != 0.0 || prev[2 * (a * d + c) + 1] != 0.0) pc = c;
+    same = pc == col;
+  }
   const int any = __syncthreads_or(multi);
-  if (threadIdx.x == 0) gp(P.mok)[j] = (!any && !(P.flags & CTRL_DENSE)) ? 1 : 0;
+  // A bijection when every column is hit once (empty rows count at their own
+  // column, with a zero entry); then minv[j][col_j(a)] = a.
+  const int bij = __syncthreads_and(a >= D || hits[a] == 1);
+  const int all_same = __syncthreads_and(same) && j > 0;
+  if (P.minv && a < D) gp(P.minv)[(size_t)j * D + col] = a;
+  if (threadIdx.x == 0)
+    gp(P.mok)[j] = (!any && !(P.flags & CTRL_DENSE)) ? (1 | (bij && P.minv ? 2 : 0) | (all_same ? 4 : 0)) : 0;
 }
 
 // True when every control of the problem has a usable row table (at most
@@ -123,6 +144,14 @@ __device__ __forceinline__ void control_rows(const ProbDesc& P, int j, const dou
 __device__ __forceinline__ bool controls_monomial(const ProbDesc& P) {
   for (int j = 0; j < P.m; ++j)
     if (!gp(P.mok)[j]) return false;
+  return true;
+}
+
+// True when every control's row table is also a bijection from rows to
+// columns (minv holds its inverse).  Uniform across the workgroup.
+__device__ __forceinline__ bool controls_permutation(const ProbDesc& P) {
+  for (int j = 0; j < P.m; ++j)
+    if (!(gp(P.mok)[j] & 2)) return false;
   return true;
 }
 
@@ -1101,6 +1130,102 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 
 // ---------------------------------------------------------------- adjoint / gradient
 
+// The gradient from only the entries of Z = E + X2 C2 + S C1 that the
+// controls read (s = 0, FP32, every control a weighted permutation: Pauli
+// strings).  Control j reads Z[a][b] at b = col_j(a), once per column b, so
+// the lane that holds column b of the panels (wavefront b / 16, lane b % 16
+// of each lane group) forms z = Z[minv_j(b)][b] as the dot product of row
+// minv_j(b) of X2 and of S (LDS) with its own entries of C2 and C1, the four
+// lane groups each taking their 16 of the d rows and then summing; E[a][b]
+// comes from the lane that holds it.  That is 2 d m complex multiply-adds per
+// column on the vector ALU in place of the last two products (d^3 each),
+// then T_j = sum_b conj(z) val_j(minv_j(b)) in FP64 as in gradient_epilogue.
+template <int D>
+constexpr int kSampleGroup = 4;  // controls per reduction
+
+template <int D>
+__device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const Panel<float, D>& E,
+                                                 const Panel<float, D>& C1, const Panel<float, D>& C2,
+                                                 const void* x2lds, const void* slds, double* red,
+                                                 const Lane& L) {
+  constexpr int NV = D / 16;
+  constexpr int SD = Mat<float, D>::SD;
+  constexpr int G = kSampleGroup<D>;
+  const float* xr = static_cast<const float*>(x2lds);
+  const float* xi = xr + D * SD;
+  const float* yr = static_cast<const float*>(slds);
+  const float* yi = yr + D * SD;
+  const int b = 16 * L.w + L.c16;
+  const float* mv = reinterpret_cast<const float*>(P.mval);
+  float zr = 0.f, zi = 0.f;
+  for (int j0 = 0, grp = 0; j0 < P.m; j0 += G, ++grp) {
+    // the group's table entries first: two round trips per group, not per control
+    int ag[G], fl[G];
+    float hrg[G], hig[G];
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = min(j0 + jj, P.m - 1);
+      ag[jj] = gp(P.minv)[(size_t)j * D + b];
+      fl[jj] = gp(P.mok)[j];
+    }
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      const size_t e = (size_t)min(j0 + jj, P.m - 1) * D + ag[jj];
+      hrg[jj] = gp(mv)[2 * e];
+      hig[jj] = gp(mv)[2 * e + 1];
+    }
+    double v[2 * G];
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      const int a = ag[jj];
+      // a control with the previous one's columns (in this group) reads the
+      // same entries of Z: z is reused (uniform over the workgroup)
+      if (jj == 0 || j0 + jj >= P.m || !(fl[jj] & 4)) {
+        // LDS row a at the columns of this lane's panel rows 16 rb + 4 g + r
+        const int base = a * SD + 4 * L.g;
+        float pr[4] = {0.f, 0.f, 0.f, 0.f}, pi[4] = {0.f, 0.f, 0.f, 0.f};  // one chain per r
+#pragma unroll
+        for (int rb = 0; rb < NV; ++rb) {
+          const f4 ar = Prec<float>::ld4(xr + base + 16 * rb), ai = Prec<float>::ld4(xi + base + 16 * rb);
+          const f4 br = Prec<float>::ld4(yr + base + 16 * rb), bi = Prec<float>::ld4(yi + base + 16 * rb);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool own = 16 * rb + 4 * L.g + r == a;
+            pr[r] += own ? E.re[rb][r] : 0.f;
+            pi[r] += own ? E.im[rb][r] : 0.f;
+            pr[r] = fmaf(ar[r], C2.re[rb][r], pr[r]);
+            pr[r] = fmaf(-ai[r], C2.im[rb][r], pr[r]);
+            pr[r] = fmaf(br[r], C1.re[rb][r], pr[r]);
+            pr[r] = fmaf(-bi[r], C1.im[rb][r], pr[r]);
+            pi[r] = fmaf(ar[r], C2.im[rb][r], pi[r]);
+            pi[r] = fmaf(ai[r], C2.re[rb][r], pi[r]);
+            pi[r] = fmaf(br[r], C1.im[rb][r], pi[r]);
+            pi[r] = fmaf(bi[r], C1.re[rb][r], pi[r]);
+          }
+        }
+        zr = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+        zi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+        zr += __shfl_xor(zr, 16, 64);
+        zi += __shfl_xor(zi, 16, 64);
+        zr += __shfl_xor(zr, 32, 64);
+        zi += __shfl_xor(zi, 32, 64);
+      }
+      const float hr = hrg[jj], hi = hig[jj];
+      double tr = 0, ti = 0;
+      if (L.g == 0 && j0 + jj < P.m) {  // conj(z) h, once per column
+        tr = (double)zr * hr + (double)zi * hi;
+        ti = (double)zr * hi - (double)zi * hr;
+      }
+      v[2 * jj] = tr;
+      v[2 * jj + 1] = ti;
+    }
+    epilogue_publish<D / 16, G>(P, k, j0, grp, v, L, red);
+  }
+}
+
+template <typename T, int D, typename Ops>
+constexpr bool kSampleLast = std::is_same<Ops, StdOps<float, D>>::value && D >= 32;
+
 // One workgroup per slice.
 //  1. W_k = bloc[k] xprev[k]^dag  (one product; bloc[k] carries mc[c]).
 //  2. X = A_k^dag / 2^s in LDS buffer 0, E = W_k / 2^s in buffer 1.
@@ -1119,7 +1244,11 @@ constexpr int kAdjWaves = ((sizeof(T) == 4 && D <= 64) || (sizeof(T) == 8 && D =
 template <typename T, int D>
 constexpr bool kEarlyH = (sizeof(T) == 4 && D == 64) || (sizeof(T) == 8 && D == 32);
 
-template <typename T, int D, typename Ops, bool PERSIST>
+// MODE 0: every slice; where the sampled last step applies (kSampleLast), two
+// instances split the slices: MODE 1 takes those where it does not apply,
+// MODE 2 those where it does (s = 0, permutation controls), each returning at
+// once for the others, so that neither carries the other's registers.
+template <typename T, int D, typename Ops, bool PERSIST, int MODE = 0>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves<T, D>)))
 void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
@@ -1133,6 +1262,13 @@ void k_adjoint(Work W) {
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
   int s, q, qb;
   unpack_sq(gp(P.sq)[k], s, q, qb);
+  if constexpr (MODE != 0) {
+    const bool sampled = s == 0 && controls_permutation(P);  // uniform over the workgroup
+    if (sampled != (MODE == 2)) {
+      if constexpr (PERSIST) continue;
+      else return;
+    }
+  }
   const bool mono = controls_monomial(P);
   Panel<T, D> R1, R2, A1, A2;
 
@@ -1219,6 +1355,10 @@ void k_adjoint(Work W) {
     A1 = A2;
     A2 = R3;
   }
+  if constexpr (MODE == 2) {
+    // 4'-5'. only the entries of Z that the controls read
+    sampled_gradient<D>(P, k, R2, A1, A2, lds[0], lds[1], red, L);
+  } else {
   Ops::gemm3(R2, lds[0], A2, L, false);
   Ops::gemm3(R2, lds[1], A1, L, false);              // R2 = Q = E + X2 C2 + S C1
   if (s > 0) Ops::gemm3(R1, lds[0], A1, L, false);  // R1 = D1 = X + X2 C1
@@ -1243,6 +1383,7 @@ void k_adjoint(Work W) {
 
   // 5. inner products with the controls (FP64), then the gradient
   gradient_epilogue<T, D>(P, k, A2, L, lds[0], red, mono);
+  }
   if constexpr (!PERSIST) break;  // one item per workgroup: a single-trip loop
   __syncthreads();
   }
@@ -2229,8 +2370,19 @@ static void stage_small(int stage, const Launch& L, const Range& rg, double ur) 
     }
     case ST_ADJ: {
       Work w = L.dyn ? dyn : slice_work(L, rg);
-      if (L.dyn) hipLaunchKernelGGL((k_adjoint<T, D, Ops, true>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
-      else hipLaunchKernelGGL((k_adjoint<T, D, Ops, false>), dim3(grid_of(L, w.total, 0)), dim3(NT), 0, st, w);
+      const dim3 grid(grid_of(L, w.total, 0));
+      if constexpr (kSampleLast<T, D, Ops>) {
+        if (L.dyn) {
+          hipLaunchKernelGGL((k_adjoint<T, D, Ops, true, 2>), grid, dim3(NT), 0, st, w);
+          hipLaunchKernelGGL((k_adjoint<T, D, Ops, true, 1>), grid, dim3(NT), 0, st, w);
+        } else {
+          hipLaunchKernelGGL((k_adjoint<T, D, Ops, false, 2>), grid, dim3(NT), 0, st, w);
+          hipLaunchKernelGGL((k_adjoint<T, D, Ops, false, 1>), grid, dim3(NT), 0, st, w);
+        }
+      } else {
+        if (L.dyn) hipLaunchKernelGGL((k_adjoint<T, D, Ops, true>), grid, dim3(NT), 0, st, w);
+        else hipLaunchKernelGGL((k_adjoint<T, D, Ops, false>), grid, dim3(NT), 0, st, w);
+      }
       break;
     }
   }

@@ -6,7 +6,7 @@ import numpy as np
 import bench
 
 
-def _products_adjoint(s, q, qb, keep_x2):
+def _products_adjoint(s, q, qb, keep_x2, sampled=False):
     # W = bloc xprev^dag: one product.  Block polynomial by Paterson-Stockmeyer
     # in M^2: three products for M^2 (two when the expm kept X^2, which it
     # forms when q >= 2); the digits above the first one that needs a product
@@ -20,6 +20,8 @@ def _products_adjoint(s, q, qb, keep_x2):
     while t >= 0:
         n += 3
         t -= 1
+    if sampled and s == 0:
+        return n  # the last step's entries on the vector ALU
     n += 2 + (1 if s > 0 else 0)
     for j in range(s):
         n += 2 + (1 if j + 1 < s else 0)
@@ -55,6 +57,40 @@ def test_adjoint_product_count_matches_the_loop_structure():
                 assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, q, qb, keep)
             f = bench.slice_flops(plan, 16, 8, "fp32")  # d = 16 keeps no X^2
             assert f["adjoint_8d3"] == 8.0 * 16 ** 3 * _products_adjoint(s, q, qb, False)
+
+
+def test_sampled_last_step_is_counted_where_it_runs():
+    from workloads import make_config
+
+    runs = bench.permutation_runs(make_config(3, N=4).Hc)
+    assert runs == 6  # X_i and Y_i share their columns: two runs per group of four
+    for s in range(0, 3):
+        for qb in range(2, 9):
+            q = max(qb - 1, 1)
+            plan = np.array([[s, q, qb]], dtype=np.int32)
+            f = bench.slice_flops(plan, 64, 12, "fp32", runs)
+            assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, q, qb, True, True)
+            assert f["adjoint_valu"] == (16.0 * 64 * 64 * runs if s == 0 else 0.0)
+            # not at d = 16 or d = 128, nor in FP64 or split BF16
+            for d, prec, keep in ((16, "fp32", False), (128, "fp32", True), (64, "fp64", False),
+                                  (64, "bf16x3", False)):
+                g = bench.slice_flops(plan, d, 12, prec, runs)
+                assert g["adjoint_8d3"] == 8.0 * d ** 3 * _products_adjoint(s, q, qb, keep) and g["adjoint_valu"] == 0
+
+
+def test_permutation_runs():
+    from workloads import make_config, random_hermitian
+
+    assert bench.permutation_runs(make_config(2, N=4).Hc) == 4
+    assert bench.permutation_runs(make_config(4, N=4).Hc) == 7  # 14 controls, the last group X_6 and Y_6
+    rng = np.random.default_rng(3)
+    assert bench.permutation_runs(np.stack([random_hermitian(8, rng)])) is None
+    H = np.zeros((4, 4), dtype=np.complex128)
+    H[0, 1] = H[1, 0] = H[2, 2] = 1.0  # row 3 empty: a permutation with an empty row
+    assert bench.permutation_runs(np.stack([H, 2 * H])) == 1
+    H2 = H.copy()
+    H2[3, 1] = 1.0  # column 1 hit twice
+    assert bench.permutation_runs(np.stack([H2])) is None
 
 
 def test_expm_product_count_matches_the_loop_structure():

@@ -39,6 +39,47 @@ def test_monomial_controls_match_the_oracle(gpu_lib, prec, d, m, N):
     _check(p, prec, F, grad, ref)
 
 
+def _same_columns(H, rng):
+    """A Hermitian matrix with the nonzeros of H at the same places and other
+    values: paired entries rotated by a random phase, diagonal ones rescaled."""
+    G = H.copy()
+    d = H.shape[0]
+    for a in range(d):
+        for b in range(a + 1, d):
+            if H[a, b] != 0:
+                G[a, b] = H[a, b] * np.exp(1j * rng.uniform(0, 2 * np.pi)) * rng.uniform(0.5, 1.5)
+                G[b, a] = np.conj(G[a, b])
+        G[a, a] = H[a, a] * rng.uniform(-1.5, 1.5)
+    return G
+
+
+@pytest.mark.parametrize("d", [20, 40, 64])
+def test_controls_sharing_columns(gpu_lib, d):
+    """Runs of controls whose nonzeros sit at the same columns (as X_i and
+    Y_i do), between controls with other columns, in FP32 at s = 0: the
+    adjoint forms the entries of Z these controls read once per run (d > 16).
+    Against the oracle, and against the dense kernels on the same inputs."""
+    from paper_2208_12187_amd import qoc
+    from workloads.spin import random_monomial_hermitian
+
+    rng = np.random.default_rng(40 + d)
+    base = make_random_monomial(13, d, 2, 33, dt=0.005)
+    A = random_monomial_hermitian(d, rng)
+    B = random_monomial_hermitian(d, rng)
+    # runs: A A' | B | B' B'' | A'' ; m = 7, groups of four cut the second run
+    Hc = np.stack([A, _same_columns(A, rng), B, _same_columns(B, rng), _same_columns(B, rng),
+                   _same_columns(A, rng), B])
+    u = rng.normal(0, 0.5, (Hc.shape[0], base.N))
+    p = Problem(base.H0, Hc, u, base.dt, base.V)
+    assert qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, "fp32", True)[:, 0].max() == 0
+    print(f"[monomial] shared columns d={d}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32")
+    _check(p, "fp32", F, grad, ref)
+    Fd, gd = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", dense_controls=True)
+    assert np.max(np.abs(grad - gd)) <= 1e-4 * np.max(np.abs(ref["grad"]))
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("d,m", [(16, 20), (40, 24), (64, 20)])
 def test_many_row_table_controls(gpu_lib, prec, d, m):
