@@ -148,12 +148,17 @@ __device__ __forceinline__ bool controls_monomial(const ProbDesc& P) {
 }
 
 // True when every control's row table is also a bijection from rows to
-// columns (minv holds its inverse).  Uniform across the workgroup.
+// columns (minv holds its inverse).  (All the flags are loaded together.)
 __device__ __forceinline__ bool controls_permutation(const ProbDesc& P) {
-  for (int j = 0; j < P.m; ++j)
-    if (!(gp(P.mok)[j] & 2)) return false;
-  return true;
+  int all = 2;
+  for (int j = 0; j < P.m; ++j) all &= gp(P.mok)[j];
+  return all != 0;
 }
+
+// Bit 24 of a slice's packed plan: the FP32 adjoint may sample its last step
+// there (s = 0 and permutation controls), so that the adjoint's two instances
+// split the slices with the one load of the plan.
+constexpr int kPlanSampled = 1 << 24;
 
 // Convert the caller's complex128 matrices to the compute precision: H0 and
 // Hc[j] to planar D x D (zero padded), V to PF; also the FP64 one-norms
@@ -260,7 +265,8 @@ __global__ __launch_bounds__(256) void k_plan(Work W, double ur, int flags) {
     double th = P.norms[0];
     for (int j = 0; j < P.m; ++j) th = fma(fabs(gp(P.u)[(size_t)j * P.N + k]), gp(P.norms)[j + 1], th);
     th *= P.dt;
-    P.sq[k] = pack_plan(choose_plan(th, ur, (flags & 1) != 0, (flags & 2) != 0));
+    const SlicePlan pl = choose_plan(th, ur, (flags & 1) != 0, (flags & 2) != 0);
+    P.sq[k] = pack_plan(pl) | (pl.s == 0 && controls_permutation(P) ? kPlanSampled : 0);
   }
 }
 
@@ -1260,10 +1266,11 @@ void k_adjoint(Work W) {
   int p, k;
   split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
   const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
+  const int sqk = gp(P.sq)[k];
   int s, q, qb;
-  unpack_sq(gp(P.sq)[k], s, q, qb);
+  unpack_sq(sqk, s, q, qb);
   if constexpr (MODE != 0) {
-    const bool sampled = s == 0 && controls_permutation(P);  // uniform over the workgroup
+    const bool sampled = (sqk & kPlanSampled) != 0;  // uniform over the workgroup
     if (sampled != (MODE == 2)) {
       if constexpr (PERSIST) continue;
       else return;

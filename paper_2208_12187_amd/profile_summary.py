@@ -36,7 +36,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
-ADJOINT = "qoc::k_adjoint<float, 64, qoc::StdOps<float, 64>, false>"
+# The FP32 d = 64 adjoint stage: its instances (the slices with and without the
+# sampled last step) are summed per launch of the stage.
+ADJOINT = "qoc::k_adjoint<float, 64, qoc::StdOps<float, 64>, false"
 
 
 def short(name: str) -> str:
@@ -91,8 +93,11 @@ def bytes_table(fetch_csv: str, write_csv: str, copy_gib: float, json_out: str |
         w = sum(wv[k]) / len(wv[k])
         lines.append(f"| `{k}` | {len(fv[k])} | {f:.1f} | {w:.1f} | {f * fs * 1.024e-3:.1f} | {w * ws * 1.024e-3:.1f} |")
     if json_out:
-        f = sum(fv[ADJOINT]) / len(fv[ADJOINT])
-        w = sum(wv[ADJOINT]) / len(wv[ADJOINT])
+        inst = [k for k in fv if k.startswith(ADJOINT)]
+        if not inst:
+            raise SystemExit(f"no {ADJOINT}...> dispatch in {fetch_csv}")
+        f = sum(sum(fv[k]) / len(fv[k]) for k in inst)
+        w = sum(sum(wv[k]) / len(wv[k]) for k in inst)
         with open(json_out, "w") as fh:
             json.dump({"kernel": "k_adjoint<float, 64>", "fetch_kib": f, "write_kib": w, "fetch_scale": fs,
                        "write_scale": ws, "csrc_sha256": csrc_sha256(),
