@@ -63,7 +63,8 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str, runs=None) -> dict:
     with a matrix digit, two for the last step's top-right block, three per
     squaring), one fewer where the FP32 expm keeps X^2 for the FP32 adjoint
     (d > 16, q >= 2), and two fewer where the FP32 adjoint samples its last step
-    (16 < d <= 64, s = 0, `runs` not None: permutation controls), which costs
+    (d > 16, at d = 128 with m <= 16, s = 0, `runs` not None: permutation
+    controls), which costs
     16 d^2 runs real flops on the vector ALU instead ("adjoint_valu").
     A product costs 8 d^3 real flops in the four-product form and 6 d^3 in
     the three-product (Gauss) form.  FP32 and FP64 use the latter in every
@@ -85,7 +86,8 @@ def slice_flops(plan: np.ndarray, d: int, m: int, prec: str, runs=None) -> dict:
         n_exp = q - 1 + s
     keep_x2 = prec == "fp32" and d > 16
     n_adj = 6 + 3 * np.maximum(0, (qb - 3) // 2) + 3 * s - (keep_x2 * (q >= 2))
-    sampled = (s == 0) if (prec == "fp32" and 16 < d <= 64 and runs is not None) else np.zeros_like(s, dtype=bool)
+    on = prec == "fp32" and d > 16 and (d <= 64 or m <= 16) and runs is not None
+    sampled = (s == 0) if on else np.zeros_like(s, dtype=bool)
     n_adj = n_adj - 2 * sampled
     valu = float((16.0 * d * d * (runs or 0) * sampled).sum())
     return {"expm": float((g_expm * n_exp).sum()), "scan": float(2 * g_scan * len(s)),

@@ -2170,6 +2170,102 @@ __global__ __launch_bounds__(512) void k_mc128(Work W, void* scratch) {
   }
 }
 
+// The sampled last step at D = 128 (FP32, s = 0, permutation controls, at most
+// kSample128Max controls): as sampled_gradient, with the operands in scratch.
+// X2 and S take the LDS in turn (the whole FP32 matrix fits), so every
+// column set's partial sums stay in registers between the two passes: pass 1
+// adds X2 C2, pass 2 S C1 and E; C1, C2 and E are read one row block of this
+// wavefront's own panels at a time.
+constexpr int kSample128Max = 16;
+
+__device__ __forceinline__ void sampled_gradient128(const ProbDesc& P, int k, const Lane& L, float* lds, double* red,
+                                                    const float* X2, const float* S, const float* C1,
+                                                    const float* C2, const float* E, bool x2_staged) {
+  using K = K128<float>;
+  constexpr int MS = kSample128Max;
+  constexpr int G = kEpiGroup;
+  const float* lim = lds + K::D * K::SD;
+  const int b = 16 * L.w + L.c16;
+  const int m = P.m;
+  int aj[MS];
+  unsigned fresh = 0;  // bit j: control j starts a column set (else it reuses j - 1's)
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    aj[j] = j < m ? gp(P.minv)[(size_t)j * K::D + b] : 0;
+    if (j < m && (j % G == 0 || !(gp(P.mok)[j] & 4))) fresh |= 1u << j;
+  }
+  float zr[MS], zi[MS];
+#pragma unroll
+  for (int j = 0; j < MS; ++j) zr[j] = zi[j] = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 || !x2_staged) {
+      __syncthreads();
+      stage128<float, false>(lds, pass == 0 ? X2 : S, 0, L);
+      __syncthreads();
+    }
+    const float* Cp = pass == 0 ? C2 : C1;
+#pragma unroll 1
+    for (int rb = 0; rb < K::RB; ++rb) {
+      f4 cr, ci, er, ei;
+      pf_rb_load<float>(cr, ci, Cp, L.w, rb, L.lane);
+      if (pass == 1) pf_rb_load<float>(er, ei, E, L.w, rb, L.lane);
+      const int col = 16 * rb + 4 * L.g;
+#pragma unroll
+      for (int j = 0; j < MS; ++j) {
+        if (fresh & (1u << j)) {  // uniform over the workgroup
+          const f4 ar = Prec<float>::ld4(lds + aj[j] * K::SD + col), ai = Prec<float>::ld4(lim + aj[j] * K::SD + col);
+          float pr = zr[j], pi = zi[j];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (pass == 1 && col + r == aj[j]) {
+              pr += er[r];
+              pi += ei[r];
+            }
+            pr = fmaf(ar[r], cr[r], pr);
+            pr = fmaf(-ai[r], ci[r], pr);
+            pi = fmaf(ar[r], ci[r], pi);
+            pi = fmaf(ai[r], cr[r], pi);
+          }
+          zr[j] = pr;
+          zi[j] = pi;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < MS; ++j) {
+    if (fresh & (1u << j)) {
+      zr[j] += __shfl_xor(zr[j], 16, 64);
+      zi[j] += __shfl_xor(zi[j], 16, 64);
+      zr[j] += __shfl_xor(zr[j], 32, 64);
+      zi[j] += __shfl_xor(zi[j], 32, 64);
+    } else if (j > 0) {
+      zr[j] = zr[j - 1];
+      zi[j] = zi[j - 1];
+    }
+  }
+  const float* mv = reinterpret_cast<const float*>(P.mval);
+#pragma unroll
+  for (int j0 = 0; j0 < MS; j0 += G) {
+    if (j0 >= m) break;
+    double v[2 * G];
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      const int j = j0 + jj;
+      double tr = 0, ti = 0;
+      if (L.g == 0 && j < m) {  // conj(z) h, once per column
+        const size_t e = (size_t)j * K::D + aj[j];
+        const float hr = gp(mv)[2 * e], hi = gp(mv)[2 * e + 1];
+        tr = (double)zr[j] * hr + (double)zi[j] * hi;
+        ti = (double)zr[j] * hi - (double)zi[j] * hr;
+      }
+      v[2 * jj] = tr;
+      v[2 * jj + 1] = ti;
+    }
+    epilogue_publish<8, G>(P, k, j0, j0 / G, v, L, red);
+  }
+}
+
 // Same steps as k_adjoint, with the chain state in scratch (see above).
 template <typename T>
 __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
@@ -2187,8 +2283,9 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
     int p, k;
     split_item(item, W.rg.s_lo, W.rg.s_n, I.start, I.nprob, p, k);
     const ProbDesc P = W.descs[I.desc(p)];  // a copy: stores cannot alias it
+    const int sqk = gp(P.sq)[k];
     int s, q, qb;
-    unpack_sq(gp(P.sq)[k], s, q, qb);
+    unpack_sq(sqk, s, q, qb);
     Panel<T, 128> acc;
     // W = bloc[k] xprev[k]^dag (bloc carries mc[c])
     transpose128<T>(S0, lds, pf_mat<T, 128>(P.xprev, k - W.rg.kbase), L);
@@ -2261,6 +2358,13 @@ __global__ __launch_bounds__(512) void k_adjoint128(Work W, void* scratch) {
       gemm128<T, false, k128Gauss<T>>(acc, lds, S0, SR1, L, false, false);
       panel_store(SR1, acc, L);  // a I + b X + X2 C1
       x2_staged = true;
+    }
+    if constexpr (sizeof(T) == 4) {
+      if ((sqk & kPlanSampled) && P.m <= kSample128Max) {  // s = 0: only the entries the controls read
+        sampled_gradient128(P, k, L, lds, red, S0, S1, SR1, SR2, SE, x2_staged);
+        __syncthreads();
+        continue;
+      }
     }
     // Q = E + X2 C2 + S C1 and, when squaring follows, D1 = X + X2 C1 (into
     // S1 once every wavefront has staged S; Q waits in the own panel of SE).

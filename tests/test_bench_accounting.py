@@ -71,10 +71,13 @@ def test_sampled_last_step_is_counted_where_it_runs():
             f = bench.slice_flops(plan, 64, 12, "fp32", runs)
             assert f["adjoint_8d3"] == 8.0 * 64 ** 3 * _products_adjoint(s, q, qb, True, True)
             assert f["adjoint_valu"] == (16.0 * 64 * 64 * runs if s == 0 else 0.0)
-            # not at d = 16 or d = 128, nor in FP64 or split BF16
-            for d, prec, keep in ((16, "fp32", False), (128, "fp32", True), (64, "fp64", False),
-                                  (64, "bf16x3", False)):
-                g = bench.slice_flops(plan, d, 12, prec, runs)
+            # also at d = 128 with at most 16 controls
+            g = bench.slice_flops(plan, 128, 14, "fp32", runs)
+            assert g["adjoint_8d3"] == 8.0 * 128 ** 3 * _products_adjoint(s, q, qb, True, True)
+            # not at d = 16, nor at d = 128 with more controls, nor in FP64 or split BF16
+            for d, mm, prec, keep in ((16, 12, "fp32", False), (128, 17, "fp32", True), (64, 12, "fp64", False),
+                                      (64, 12, "bf16x3", False)):
+                g = bench.slice_flops(plan, d, mm, prec, runs)
                 assert g["adjoint_8d3"] == 8.0 * d ** 3 * _products_adjoint(s, q, qb, keep) and g["adjoint_valu"] == 0
 
 
