@@ -1142,25 +1142,96 @@ __global__ __launch_bounds__(4 * D) void k_mc(Work W) {
 // the lane that holds column b of the panels (wavefront b / 16, lane b % 16
 // of each lane group) forms z = Z[minv_j(b)][b] as the dot product of row
 // minv_j(b) of X2 and of S (LDS) with its own entries of C2 and C1, the four
-// lane groups each taking their 16 of the d rows and then summing; E[a][b]
-// comes from the lane that holds it.  That is 2 d m complex multiply-adds per
-// column on the vector ALU in place of the last two products (d^3 each),
-// then T_j = sum_b conj(z) val_j(minv_j(b)) in FP64 as in gradient_epilogue.
+// lane groups each taking their 16 of the d rows and then summing.  E[a][b]
+// of the first kSampleGather controls was gathered from LDS before S took
+// E's place (sample_gather); later controls take it from the lane that holds
+// it, inside the dot product.  That is 2 d m complex multiply-adds per column
+// on the vector ALU in place of the last two products (d^3 each), then
+// T_j = sum_b conj(z) val_j(minv_j(b)) in FP64 as in gradient_epilogue.
 template <int D>
 constexpr int kSampleGroup = 4;  // controls per reduction
+// Controls whose entries E[minv_j(b)][b] are gathered (8 KB of LDS at D = 64,
+// which still fits two workgroups per CU).
+constexpr int kSampleGather = 16;
+
+// Thread t: column t % D of controls t / D + 4 i.  The rows are loaded before
+// the block's square is formed and the entries read after it, while E is
+// still in LDS.
+template <int D>
+__device__ __forceinline__ void sample_rows(const ProbDesc& P, int (&ga)[kSampleGather / 4]) {
+#pragma unroll
+  for (int i = 0; i < kSampleGather / 4; ++i) {
+    const int j = (int)threadIdx.x / D + 4 * i;
+    ga[i] = j < P.m ? gp(P.minv)[(size_t)j * D + threadIdx.x % D] : 0;
+  }
+}
 
 template <int D>
-__device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const Panel<float, D>& E,
-                                                 const Panel<float, D>& C1, const Panel<float, D>& C2,
-                                                 const void* x2lds, const void* slds, double* red,
-                                                 const Lane& L) {
+__device__ __forceinline__ void sample_gather(const ProbDesc& P, const int (&ga)[kSampleGather / 4], const void* elds,
+                                              float* eg) {
+  const float* er = static_cast<const float*>(elds);
+  const float* ei = er + D * Mat<float, D>::SD;
+  const int b = threadIdx.x % D;
+#pragma unroll
+  for (int i = 0; i < kSampleGather / 4; ++i) {
+    const int j = (int)threadIdx.x / D + 4 * i;
+    if (j < P.m) {
+      const int off = lds_off<float, D>(ga[i], b);
+      eg[2 * (j * D + b)] = er[off];
+      eg[2 * (j * D + b) + 1] = ei[off];
+    }
+  }
+}
+
+// Partial sums of z over this lane group's rows; WITH_E also picks E[a][b]
+// into (er, ei) in the lane that holds it (zero elsewhere), so that it is
+// added after the sum over the lane groups, as the gathered entry is: the
+// two forms give the same bits.
+template <int D, bool WITH_E>
+__device__ __forceinline__ void sampled_dot(float& zr, float& zi, float& er, float& ei, int a, const float* xr,
+                                            const float* xi, const float* yr, const float* yi,
+                                            const Panel<float, D>& E, const Panel<float, D>& C1,
+                                            const Panel<float, D>& C2, const Lane& L) {
   constexpr int NV = D / 16;
   constexpr int SD = Mat<float, D>::SD;
+  // LDS row a at the columns of this lane's panel rows 16 rb + 4 g + r
+  const int base = a * SD + 4 * L.g;
+  float pr[4] = {0.f, 0.f, 0.f, 0.f}, pi[4] = {0.f, 0.f, 0.f, 0.f};  // one chain per r
+#pragma unroll
+  for (int rb = 0; rb < NV; ++rb) {
+    const f4 ar = Prec<float>::ld4(xr + base + 16 * rb), ai = Prec<float>::ld4(xi + base + 16 * rb);
+    const f4 br = Prec<float>::ld4(yr + base + 16 * rb), bi = Prec<float>::ld4(yi + base + 16 * rb);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if constexpr (WITH_E) {
+        const bool own = 16 * rb + 4 * L.g + r == a;
+        er = own ? E.re[rb][r] : er;
+        ei = own ? E.im[rb][r] : ei;
+      }
+      pr[r] = fmaf(ar[r], C2.re[rb][r], pr[r]);
+      pr[r] = fmaf(-ai[r], C2.im[rb][r], pr[r]);
+      pr[r] = fmaf(br[r], C1.re[rb][r], pr[r]);
+      pr[r] = fmaf(-bi[r], C1.im[rb][r], pr[r]);
+      pi[r] = fmaf(ar[r], C2.im[rb][r], pi[r]);
+      pi[r] = fmaf(ai[r], C2.re[rb][r], pi[r]);
+      pi[r] = fmaf(br[r], C1.im[rb][r], pi[r]);
+      pi[r] = fmaf(bi[r], C1.re[rb][r], pi[r]);
+    }
+  }
+  zr = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+  zi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
+}
+
+template <int D, bool GATHERED>
+__device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const Panel<float, D>& E,
+                                                 const Panel<float, D>& C1, const Panel<float, D>& C2,
+                                                 const void* x2lds, const void* slds, const float* eg,
+                                                 double* red, const Lane& L) {
   constexpr int G = kSampleGroup<D>;
   const float* xr = static_cast<const float*>(x2lds);
-  const float* xi = xr + D * SD;
+  const float* xi = xr + D * Mat<float, D>::SD;
   const float* yr = static_cast<const float*>(slds);
-  const float* yi = yr + D * SD;
+  const float* yi = yr + D * Mat<float, D>::SD;
   const int b = 16 * L.w + L.c16;
   const float* mv = reinterpret_cast<const float*>(P.mval);
   float zr = 0.f, zi = 0.f;
@@ -1183,38 +1254,33 @@ __device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const
     double v[2 * G];
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
-      const int a = ag[jj];
       // a control with the previous one's columns (in this group) reads the
       // same entries of Z: z is reused (uniform over the workgroup)
       if (jj == 0 || j0 + jj >= P.m || !(fl[jj] & 4)) {
-        // LDS row a at the columns of this lane's panel rows 16 rb + 4 g + r
-        const int base = a * SD + 4 * L.g;
-        float pr[4] = {0.f, 0.f, 0.f, 0.f}, pi[4] = {0.f, 0.f, 0.f, 0.f};  // one chain per r
-#pragma unroll
-        for (int rb = 0; rb < NV; ++rb) {
-          const f4 ar = Prec<float>::ld4(xr + base + 16 * rb), ai = Prec<float>::ld4(xi + base + 16 * rb);
-          const f4 br = Prec<float>::ld4(yr + base + 16 * rb), bi = Prec<float>::ld4(yi + base + 16 * rb);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const bool own = 16 * rb + 4 * L.g + r == a;
-            pr[r] += own ? E.re[rb][r] : 0.f;
-            pi[r] += own ? E.im[rb][r] : 0.f;
-            pr[r] = fmaf(ar[r], C2.re[rb][r], pr[r]);
-            pr[r] = fmaf(-ai[r], C2.im[rb][r], pr[r]);
-            pr[r] = fmaf(br[r], C1.re[rb][r], pr[r]);
-            pr[r] = fmaf(-bi[r], C1.im[rb][r], pr[r]);
-            pi[r] = fmaf(ar[r], C2.im[rb][r], pi[r]);
-            pi[r] = fmaf(ai[r], C2.re[rb][r], pi[r]);
-            pi[r] = fmaf(br[r], C1.im[rb][r], pi[r]);
-            pi[r] = fmaf(bi[r], C1.re[rb][r], pi[r]);
-          }
+        const int j = min(j0 + jj, P.m - 1);
+        const bool gathered = GATHERED && j < kSampleGather;
+        float er = 0.f, ei = 0.f;
+        if constexpr (GATHERED) {
+          if (gathered) sampled_dot<D, false>(zr, zi, er, ei, ag[jj], xr, xi, yr, yi, E, C1, C2, L);
+          else sampled_dot<D, true>(zr, zi, er, ei, ag[jj], xr, xi, yr, yi, E, C1, C2, L);
+        } else {
+          sampled_dot<D, true>(zr, zi, er, ei, ag[jj], xr, xi, yr, yi, E, C1, C2, L);
         }
-        zr = (pr[0] + pr[1]) + (pr[2] + pr[3]);
-        zi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
         zr += __shfl_xor(zr, 16, 64);
         zi += __shfl_xor(zi, 16, 64);
         zr += __shfl_xor(zr, 32, 64);
         zi += __shfl_xor(zi, 32, 64);
+        if (gathered) {
+          er = eg[2 * (j * D + b)];
+          ei = eg[2 * (j * D + b) + 1];
+        } else {  // one nonzero among the lane groups: the sum is exact
+          er += __shfl_xor(er, 16, 64);
+          ei += __shfl_xor(ei, 16, 64);
+          er += __shfl_xor(er, 32, 64);
+          ei += __shfl_xor(ei, 32, 64);
+        }
+        zr += er;
+        zi += ei;
       }
       const float hr = hrg[jj], hi = hig[jj];
       double tr = 0, ti = 0;
@@ -1260,6 +1326,9 @@ void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
   __shared__ double red[2 * kEpiDense * 2 * NW];
+  // sample_gather (not in the persistent grid, whose registers it would spill)
+  constexpr bool GATHER = MODE == 2 && !PERSIST;
+  __shared__ __align__(16) float eg[GATHER ? 2 * kSampleGather * D : 1];
   Lane L;
   const Items I(W);
   for (int item = blockIdx.x; item < I.total; item += gridDim.x) {
@@ -1316,6 +1385,8 @@ void k_adjoint(Work W) {
   //    Each block product by M^2 takes three d x d products, the last one
   //    only the blocks used next.
   Panel<T, D> R3;
+  int ga[kSampleGather / 4];
+  if constexpr (GATHER) sample_rows<D>(P, ga);
   Ops::load(R1, X, L);  // R1 = X, R2 = E
   // A1 = X2: kept by the expm pass where it keeps H_k and forms its own
   // square (q >= 2; for Hermitian H_k its X X equals this X X); general
@@ -1325,6 +1396,7 @@ void k_adjoint(Work W) {
   else Ops::gemm3(A1, X, R1, L, true);
   Ops::gemm3(A2, X, R2, L, true);
   Ops::gemm3(A2, E, R1, L, false);  // A2 = S
+  if constexpr (GATHER) sample_gather<D>(P, ga, E, eg);
   __syncthreads();                  // X and E are read: M^2 takes their place
   Ops::store(lds[0], A1, L);
   Ops::store(lds[1], A2, L);
@@ -1364,7 +1436,7 @@ void k_adjoint(Work W) {
   }
   if constexpr (MODE == 2) {
     // 4'-5'. only the entries of Z that the controls read
-    sampled_gradient<D>(P, k, R2, A1, A2, lds[0], lds[1], red, L);
+    sampled_gradient<D, GATHER>(P, k, R2, A1, A2, lds[0], lds[1], eg, red, L);
   } else {
   Ops::gemm3(R2, lds[0], A2, L, false);
   Ops::gemm3(R2, lds[1], A1, L, false);              // R2 = Q = E + X2 C2 + S C1
