@@ -80,6 +80,37 @@ def test_controls_sharing_columns(gpu_lib, d):
     assert np.max(np.abs(grad - gd)) <= 1e-4 * np.max(np.abs(ref["grad"]))
 
 
+@pytest.mark.parametrize("d", [40, 64])
+def test_sampled_step_beyond_the_gathered_controls(gpu_lib, d):
+    """FP32 at s = 0 with 20 permutation controls: the sampled last step
+    takes E[a][b] of the first 16 controls from a table gathered in LDS and
+    that of the others from the registers of the lane that holds it.  Both
+    against the oracle, against the dense kernels, and the serving engine
+    (whose persistent grid takes E from the registers for every control)
+    bit for bit against the host entry."""
+    from paper_2208_12187_amd import qoc
+
+    p = make_random_monomial(21, d, 20, 40, dt=0.005)
+    assert qoc.slice_plan(p.H0, p.Hc, p.u, p.dt, "fp32", True)[:, 0].max() == 0
+    print(f"[monomial] sampled, 20 controls d={d}", flush=True)
+    ref = oracle.grape_ref(p)
+    F, grad = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32")
+    _check(p, "fp32", F, grad, ref)
+    Fd, gd = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", dense_controls=True)
+    assert np.max(np.abs(grad - gd)) <= 1e-4 * np.max(np.abs(ref["grad"]))
+    eng = qoc.Engine("fp32", pool_bytes=1 << 30, host_bytes=1 << 28, max_active=2)
+    rid = eng.submit(p.H0, p.Hc, p.u, p.dt, p.V)
+    out = None
+    while out is None:
+        eng.step(wait=True)
+        for r, Fe in eng.poll():
+            if r == rid:
+                out = (Fe, eng.fetch(r))
+    eng.close()
+    F_api, g_api = qoc.gradient(p.H0, p.Hc, p.u, p.dt, p.V, "fp32", chunk=qoc.engine_chunk(p.d, p.N))
+    assert out[0] == F_api and np.array_equal(out[1], g_api)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("d,m", [(16, 20), (40, 24), (64, 20)])
 def test_many_row_table_controls(gpu_lib, prec, d, m):
