@@ -1222,6 +1222,34 @@ __device__ __forceinline__ void sampled_dot(float& zr, float& zi, float& er, flo
   zi = (pi[0] + pi[1]) + (pi[2] + pi[3]);
 }
 
+// The sampled step's reduction: each group's per-wavefront sums go to their
+// own slot of the reduction array (epilogue_publish's layout), and one
+// barrier publishes every kSampleSlots groups at once.
+constexpr int kSampleSlots = 2 * kEpiDense / kSampleGroup<64>;
+
+template <int NWAVES, int G>
+__device__ __forceinline__ void sample_stash(int slot, double (&v)[2 * G], const Lane& L, double* red) {
+  constexpr int V = 2 * G;
+  constexpr int SH = 6 - __builtin_ctz(V);
+  const double t = wave_sum_many<V>(v, L.lane);
+  if ((L.lane & ((1 << SH) - 1)) == 0) red[slot * V * NWAVES + (L.lane >> SH) * NWAVES + L.w] = t;
+}
+
+template <int NWAVES, int G>
+__device__ __forceinline__ void sample_flush(const ProbDesc& P, int k, int j0, int nj, const double* red) {
+  if ((int)threadIdx.x < nj) {
+    const int jj = threadIdx.x;
+    const double* rg = red + (jj / G) * 2 * G * NWAVES;
+    const int q = jj % G;
+    double a = 0, b = 0;
+    for (int w = 0; w < NWAVES; ++w) {
+      a += rg[(2 * q) * NWAVES + w];
+      b += rg[(2 * q + 1) * NWAVES + w];
+    }
+    grad_put(P, j0 + jj, k, a, b);
+  }
+}
+
 template <int D, bool GATHERED>
 __device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const Panel<float, D>& E,
                                                  const Panel<float, D>& C1, const Panel<float, D>& C2,
@@ -1234,8 +1262,11 @@ __device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const
   const float* yi = yr + D * Mat<float, D>::SD;
   const int b = 16 * L.w + L.c16;
   const float* mv = reinterpret_cast<const float*>(P.mval);
+  static_assert(G * kSampleSlots <= 4 * D, "one thread per control of a block");
   float zr = 0.f, zi = 0.f;
   for (int j0 = 0, grp = 0; j0 < P.m; j0 += G, ++grp) {
+    const int slot = grp % kSampleSlots;
+    if (slot == 0 && grp > 0) __syncthreads();  // the previous block's sums are read
     // the group's table entries first: two round trips per group, not per control
     int ag[G], fl[G];
     float hrg[G], hig[G];
@@ -1291,7 +1322,12 @@ __device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const
       v[2 * jj] = tr;
       v[2 * jj + 1] = ti;
     }
-    epilogue_publish<D / 16, G>(P, k, j0, grp, v, L, red);
+    sample_stash<D / 16, G>(slot, v, L, red);
+    if (slot == kSampleSlots - 1 || j0 + G >= P.m) {
+      __syncthreads();
+      const int jb = j0 - slot * G;  // first control of the block
+      sample_flush<D / 16, G>(P, k, jb, min(kSampleSlots * G, P.m - jb), red);
+    }
   }
 }
 
