@@ -1331,6 +1331,14 @@ __device__ __forceinline__ void sampled_gradient(const ProbDesc& P, int k, const
   }
 }
 
+// Ops::gemm3 with P accumulator chain pairs where P > 1 (StdOps only).
+template <int P, typename Ops, typename T, int D>
+__device__ __forceinline__ void gemm3p(Panel<T, D>& acc, const void* lds, const Panel<T, D>& B, const Lane& L,
+                                       bool zero_acc) {
+  if constexpr (P > 1) Ops::template gemm3<P>(acc, lds, B, L, zero_acc);
+  else Ops::gemm3(acc, lds, B, L, zero_acc);
+}
+
 template <typename T, int D, typename Ops>
 constexpr bool kSampleLast = std::is_same<Ops, StdOps<float, D>>::value && D >= 32;
 
@@ -1360,6 +1368,7 @@ template <typename T, int D, typename Ops, bool PERSIST, int MODE = 0>
 __global__ __launch_bounds__(4 * D) __attribute__((amdgpu_waves_per_eu(kAdjWaves<T, D>)))
 void k_adjoint(Work W) {
   constexpr int NW = Mat<T, D>::NW;
+  constexpr int AP = MODE == 2 ? 2 : 1;  // accumulator chain pairs of the sampling instance's products
   __shared__ __align__(16) unsigned char lds[2][Ops::BYTES];
   __shared__ double red[2 * kEpiDense * 2 * NW];
   // sample_gather (not in the persistent grid, whose registers it would spill)
@@ -1395,7 +1404,7 @@ void k_adjoint(Work W) {
   Ops::store(lds[1], A2, L);
   __syncthreads();
   Ops::load_ct(A2, lds[1], L);
-  Ops::gemm3(R2, lds[0], A2, L, true);  // R2 = W
+  gemm3p<AP, Ops>(R2, lds[0], A2, L, true);  // R2 = W
   __syncthreads();
 
   // 2. E = W / 2^s, X = A^dag / 2^s
@@ -1430,8 +1439,8 @@ void k_adjoint(Work W) {
   if (kKeepH<D> && kKeepX2<T> && q >= 2 && P.x2 && !(P.flags & RUN_GENERAL))
     panel_load(A1, pf_mat<T, D>(P.x2, k - W.rg.kbase), L);
   else Ops::gemm3(A1, X, R1, L, true);
-  Ops::gemm3(A2, X, R2, L, true);
-  Ops::gemm3(A2, E, R1, L, false);  // A2 = S
+  gemm3p<AP, Ops>(A2, X, R2, L, true);
+  gemm3p<AP, Ops>(A2, E, R1, L, false);  // A2 = S
   if constexpr (GATHER) sample_gather<D>(P, ga, E, eg);
   __syncthreads();                  // X and E are read: M^2 takes their place
   Ops::store(lds[0], A1, L);
